@@ -1,0 +1,127 @@
+/*
+ * mgemm -- tiled general matrix multiply C = alpha*A*B + beta*C on AMD MI355X
+ * (gfx950), behind a plain C ABI.
+ *
+ * The operation is the paper's benchmark computation (Matthes et al., "Tuning and
+ * optimization for a variety of many-core architectures without changing a single
+ * line of implementation code using the Alpaka library", Sec. 2, Eq. 1): square in
+ * the paper, general m x n x k here.  Its work is counted as 2*m*n*k floating-point
+ * operations (Sec. 2, Eq. 2 and Eq. 4 keep the leading 2N^3 term).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Layout   Row-major.  A is m x k with lda >= max(1,k); B is k x n with
+ *          ldb >= max(1,n); C is m x n with ldc >= max(1,n).  Leading dimensions
+ *          count elements.  There are no transpose flags (the paper has none).
+ * Pointers A, B, C are DEVICE pointers on the current HIP device.  The caller owns
+ *          them; the library never frees, reallocates or keeps them after the call
+ *          (batched plans keep them until destroyed, see below).  C must not
+ *          overlap A or B.
+ * Types    MGEMM_F64: A, B, C are double.  MGEMM_F32: float (alpha, beta are
+ *          rounded to float).  MGEMM_SPLIT_BF16 / MGEMM_SPLIT_FP8: A, B, C are
+ *          double; the product is emulated from bfloat16 / FP8-e4m3 slices of A
+ *          and B (Ozaki scheme), see gemm_ex.
+ * Stream   Work is enqueued on the given HIP stream (NULL: the stream set with
+ *          mgemm_set_stream, by default the null stream) and the call returns
+ *          after enqueueing.  Launch errors are reported at once; faults surface
+ *          at the caller's synchronisation.
+ * Quick    m == 0 or n == 0: nothing happens.  k == 0 or alpha == 0: C = beta*C
+ * returns  and A, B are not read.  beta == 0: C is written without being read (a
+ *          NaN already in C does not propagate).  Padding columns (ldc > n) are
+ *          never written.
+ * Errors   0 on success.  -i: argument i (1-based, BLAS "info" convention) is
+ *          invalid, e.g. -1 for m < 0, -6 for lda < max(1,k), -12 for an unknown
+ *          dtype, or a NULL pointer whose matrix is non-empty.  Positive codes are
+ *          run-time errors: MGEMM_ERR_HIP (text in mgemm_last_error()),
+ *          MGEMM_ERR_NOMEM, MGEMM_ERR_NONFINITE (split paths: NaN or Inf in A or
+ *          B), MGEMM_ERR_NOCONFIG, MGEMM_ERR_PLAN.  On any error C is untouched.
+ * Threads  Calls may come from several host threads; the error text is
+ *          per thread.  Concurrent calls that share a split-path workspace on
+ *          one device are serialised by the library.
+ */
+#ifndef MGEMM_H
+#define MGEMM_H
+
+#include <stdint.h>
+
+#define MGEMM_API __attribute__((visibility("default")))
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MGEMM_F64 = 0,
+    MGEMM_F32 = 1,
+    MGEMM_SPLIT_BF16 = 2,
+    MGEMM_SPLIT_FP8 = 3
+} mgemm_dtype;
+
+enum {
+    MGEMM_OK = 0,
+    MGEMM_ERR_HIP = 1,
+    MGEMM_ERR_NOMEM = 2,
+    MGEMM_ERR_NONFINITE = 3,
+    MGEMM_ERR_NOCONFIG = 4,
+    MGEMM_ERR_PLAN = 5
+};
+
+/*
+ * A tile configuration (the paper's tuning parameters, Sec. 2.1 Listing 1 and
+ * Sec. 3 Tab. 4: tile size T and elements per thread, generalised).
+ *   bm, bn, bk        work-group tile of C (bm x bn) and depth of one k-step.
+ *   waves             64-lane wavefronts per work-group.
+ *   elems_per_thread  contiguous elements one thread copies per global->LDS
+ *                     load (the paper's element layer).
+ *   double_buffer     1: two LDS stages, the next k-step's tiles are loaded while
+ *                     the current one is multiplied; 0: one stage.
+ */
+typedef struct {
+    int32_t bm, bn, bk, waves, elems_per_thread, double_buffer;
+} mgemm_cfg;
+
+/* C = alpha*A*B + beta*C (Eq. 1) with the library's choice of tile configuration,
+ * on the library's current stream.  Arguments are numbered 1..12 as written. */
+MGEMM_API int32_t gemm(int64_t m, int64_t n, int64_t k, double alpha,
+             const void *A, int64_t lda, const void *B, int64_t ldb,
+             double beta, void *C, int64_t ldc, int32_t dtype);
+
+/* gemm with an explicit configuration (cfg == NULL: the library's choice; a cfg
+ * that is not in the registry for dtype gives -13) and stream (argument 14,
+ * a hipStream_t; NULL: the current library stream).  The split dtypes slice A and
+ * B in a library-owned device workspace that grows on demand (MGEMM_ERR_NOMEM if
+ * it cannot) and is kept until mgemm_release_workspace() or unload. */
+MGEMM_API int32_t gemm_ex(int64_t m, int64_t n, int64_t k, double alpha,
+                const void *A, int64_t lda, const void *B, int64_t ldb,
+                double beta, void *C, int64_t ldc, int32_t dtype,
+                const mgemm_cfg *cfg, void *stream);
+
+/* Sets the stream used when a call passes NULL; returns 0. */
+MGEMM_API int32_t mgemm_set_stream(void *stream);
+
+/* Text of the last error on this host thread ("" if none).  The pointer stays
+ * valid until the next call on this thread. */
+MGEMM_API const char *mgemm_last_error(void);
+
+/* Number of registered tile configurations for dtype (negative: bad dtype). */
+MGEMM_API int32_t mgemm_config_count(int32_t dtype);
+
+/* Copies registered configuration i of dtype into *out; 0 or -2 / -3. */
+MGEMM_API int32_t mgemm_config_get(int32_t dtype, int32_t i, mgemm_cfg *out);
+
+/* Frees the split-path workspace of the current device; 0 on success. */
+MGEMM_API int32_t mgemm_release_workspace(void);
+
+/* Diagnostic: one matrix-core step on one wave with the fragment layout the
+ * tiled kernels assume (lane l supplies A[l%16][l/16] and B[l/16][l%16] and
+ * receives D[4*(l/16)+r][l%16] in accumulator element r).  dtype is MGEMM_F64 or
+ * MGEMM_F32; A (16x4), B (4x16) and D (16x16) are row-major device buffers; on
+ * a correct layout D = A*B.  Returns 0, -1 (dtype) or -2 (NULL buffer). */
+MGEMM_API int32_t mgemm_probe_mfma(int32_t dtype, const void *A, const void *B, void *D,
+                                   void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MGEMM_H */

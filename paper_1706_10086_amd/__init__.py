@@ -1,0 +1,187 @@
+"""mgemm: tiled GEMM C = alpha*A*B + beta*C on AMD MI355X (gfx950).
+
+A thin ctypes binding of ``libmgemm.so`` (built in-tree by ``build.py``).  Every
+step of the computation runs in the library's HIP kernels; this module only
+marshals arguments.  PyTorch is used for device memory and streams.  If the
+library has not been built, importing works but every call raises
+``MgemmNotBuilt`` -- there is no fallback.
+
+Entry points mirror ``include/mgemm.h``:
+
+* ``gemm_raw`` / ``gemm_ex_raw``: the C functions with integer pointers.
+* ``gemm(A, B, C, alpha, beta, dtype, cfg, stream)``: the same on torch tensors.
+* ``configs(dtype)``: the registered tile configurations.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmgemm.so")
+
+F64, F32, SPLIT_BF16, SPLIT_FP8 = 0, 1, 2, 3
+DTYPE_NAMES = {F64: "f64", F32: "f32", SPLIT_BF16: "split_bf16", SPLIT_FP8: "split_fp8"}
+ERR_HIP, ERR_NOMEM, ERR_NONFINITE, ERR_NOCONFIG, ERR_PLAN = 1, 2, 3, 4, 5
+
+# Every symbol include/mgemm.h declares.
+EXPORTED = [
+    "gemm", "gemm_ex", "mgemm_set_stream", "mgemm_last_error", "mgemm_config_count",
+    "mgemm_config_get", "mgemm_release_workspace", "mgemm_probe_mfma",
+]
+
+
+class MgemmNotBuilt(RuntimeError):
+    pass
+
+
+class MgemmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"mgemm error {code}: {msg}")
+        self.code = code
+
+
+class Cfg(ctypes.Structure):
+    _fields_ = [("bm", ctypes.c_int32), ("bn", ctypes.c_int32), ("bk", ctypes.c_int32),
+                ("waves", ctypes.c_int32), ("elems_per_thread", ctypes.c_int32),
+                ("double_buffer", ctypes.c_int32)]
+
+    def as_tuple(self):
+        return (self.bm, self.bn, self.bk, self.waves, self.elems_per_thread, self.double_buffer)
+
+    def __repr__(self):
+        return "Cfg(%d,%d,%d,w%d,e%d,d%d)" % self.as_tuple()
+
+
+_lib = None
+
+
+def lib():
+    """Loads libmgemm.so (once) and declares its prototypes."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise MgemmNotBuilt(f"{LIB_PATH} is missing: run `python -m paper_1706_10086_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    i64, i32, d, p = ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_void_p
+    L.gemm.argtypes = [i64, i64, i64, d, p, i64, p, i64, d, p, i64, i32]
+    L.gemm.restype = i32
+    L.gemm_ex.argtypes = [i64, i64, i64, d, p, i64, p, i64, d, p, i64, i32,
+                          ctypes.POINTER(Cfg), p]
+    L.gemm_ex.restype = i32
+    L.mgemm_set_stream.argtypes = [p]
+    L.mgemm_set_stream.restype = i32
+    L.mgemm_last_error.argtypes = []
+    L.mgemm_last_error.restype = ctypes.c_char_p
+    L.mgemm_config_count.argtypes = [i32]
+    L.mgemm_config_count.restype = i32
+    L.mgemm_config_get.argtypes = [i32, i32, ctypes.POINTER(Cfg)]
+    L.mgemm_config_get.restype = i32
+    L.mgemm_release_workspace.argtypes = []
+    L.mgemm_release_workspace.restype = i32
+    L.mgemm_probe_mfma.argtypes = [i32, p, p, p, p]
+    L.mgemm_probe_mfma.restype = i32
+    _lib = L
+    return L
+
+
+def last_error() -> str:
+    return lib().mgemm_last_error().decode()
+
+
+def _check(code: int) -> int:
+    if code != 0:
+        raise MgemmError(code, last_error())
+    return code
+
+
+def _cfg_ptr(cfg):
+    if cfg is None:
+        return None
+    if isinstance(cfg, Cfg):
+        return ctypes.pointer(cfg)
+    return ctypes.pointer(Cfg(*cfg))
+
+
+def gemm_raw(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, dtype) -> int:
+    """The C ``gemm``; pointers are integers (device addresses).  Returns the code."""
+    return lib().gemm(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, dtype)
+
+
+def gemm_ex_raw(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, dtype, cfg=None, stream=None) -> int:
+    return lib().gemm_ex(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, dtype, _cfg_ptr(cfg),
+                         stream)
+
+
+def configs(dtype: int) -> list[Cfg]:
+    L = lib()
+    n = L.mgemm_config_count(dtype)
+    if n < 0:
+        raise MgemmError(n, "bad dtype")
+    out = []
+    for i in range(n):
+        c = Cfg()
+        _check(L.mgemm_config_get(dtype, i, ctypes.byref(c)))
+        out.append(c)
+    return out
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _ld(t) -> int:
+    if t.dim() != 2:
+        raise ValueError("2-D tensor expected")
+    if t.shape[1] > 1 and t.stride(1) != 1:
+        raise ValueError("unit column stride required")
+    return max(t.stride(0), 1) if t.shape[0] > 1 else max(t.shape[1], 1)
+
+
+def dtype_of(t) -> int:
+    import torch
+    if t.dtype == torch.float64:
+        return F64
+    if t.dtype == torch.float32:
+        return F32
+    raise ValueError(f"unsupported tensor dtype {t.dtype}")
+
+
+def gemm(A, B, C, alpha: float = 1.0, beta: float = 0.0, dtype: int | None = None,
+         cfg=None, stream=None):
+    """C <- alpha*A@B + beta*C on the GPU, in place; returns C.
+
+    A (m x k), B (k x n), C (m x n) are torch tensors on the current device with
+    unit column stride (row stride = leading dimension).  ``dtype`` defaults to
+    the tensors' type; SPLIT_BF16 / SPLIT_FP8 take float64 tensors."""
+    m, k = A.shape
+    k2, n = B.shape
+    if k2 != k or tuple(C.shape) != (m, n):
+        raise ValueError("shape mismatch")
+    if dtype is None:
+        dtype = dtype_of(A)
+    s = _stream_handle(stream)
+    _check(gemm_ex_raw(m, n, k, float(alpha), A.data_ptr(), _ld(A), B.data_ptr(), _ld(B),
+                       float(beta), C.data_ptr(), _ld(C), dtype, cfg, s))
+    return C
+
+
+def set_stream(stream) -> None:
+    _check(lib().mgemm_set_stream(_stream_handle(stream)))
+
+
+def release_workspace() -> None:
+    _check(lib().mgemm_release_workspace())
+
+
+def probe_mfma(dtype: int, A, B, D, stream=None) -> None:
+    """One matrix-core step (16x4 times 4x16) with the fragment layout the tiled
+    kernels assume; D receives the 16x16 product."""
+    _check(lib().mgemm_probe_mfma(dtype, A.data_ptr(), B.data_ptr(), D.data_ptr(),
+                                  _stream_handle(stream)))

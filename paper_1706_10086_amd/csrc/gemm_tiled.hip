@@ -1,0 +1,341 @@
+// Tiled GEMM C = alpha*A*B + beta*C on gfx950 matrix cores, FP64 and FP32.
+//
+// The computation is the paper's tiled GEMM (Sec. 2.1, Fig. 2): each work-group
+// owns one tile of C (Sec. 2.1: one C tile per block, the grid of Eq. 3 becoming
+// ceil(m/BM) x ceil(n/BN) work-groups); an outer loop walks the k-dimension in
+// steps of BK, staging one BM x BK tile of A and one BK x BN tile of B in LDS (the
+// tile cache of Eq. 5, here (BM*BK + BK*BN) * S bytes per stage); an inner loop
+// multiplies the staged tiles into a per-thread register sub-tile of C (the
+// thread-local temporary C tile of Fig. 2, the multiply-add of Listing 2); C is
+// read and written once at the end (the "streaming" epilogue of Fig. 2).
+//
+// gfx950 specifics (not from the paper):
+//  * the inner multiply runs on MFMA: v_mfma_f64_16x16x4_f64 for FP64 and
+//    v_mfma_f32_16x16x4_f32 for FP32, each wave owning a WM x WN block of C held
+//    as (WM/16) x (WN/16) accumulator fragments;
+//  * one lane of an MFMA fragment reads two consecutive k values of A with one
+//    16-byte LDS read and feeds them to two MFMAs; B supplies the same two k rows,
+//    so the k-sum is complete, only reordered;
+//  * LDS rows are padded so the fragment reads are free of bank conflicts;
+//  * global loads are coalesced runs of EPT consecutive elements per thread, and
+//    with double buffering the next k-step's loads are in flight while the
+//    current step is multiplied;
+//  * work-group ids are remapped so that the work-groups placed on one XCD (the
+//    hardware deals ids round-robin over the 8 XCDs) own a compact group of C
+//    tiles and share their A and B panels in that XCD's L2.
+#include "mgemm_internal.h"
+
+namespace mgemm {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef double v2d __attribute__((ext_vector_type(2)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef float v2f __attribute__((ext_vector_type(2)));
+
+// ---------------------------------------------------------------------------
+// Element-type traits: vector types and the 16x16xK MFMA step.
+// ---------------------------------------------------------------------------
+template <typename T> struct Elem;
+
+template <> struct Elem<double> {
+    typedef v2d vec2;
+    typedef v4d acc4;
+    // D += A(16x4) * B(4x16); lane l supplies A[l%16][l/16] and B[l/16][l%16].
+    __device__ static inline acc4 mma(double a, double b, acc4 c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+};
+
+template <> struct Elem<float> {
+    typedef v2f vec2;
+    typedef v4f acc4;
+    __device__ static inline acc4 mma(float a, float b, acc4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+};
+
+// alpha*acc + beta*c with each product and the sum rounded separately (no
+// contraction into a fused multiply-add), the rounding of the definition.
+template <typename T>
+__device__ inline T scale_add(T alpha, T acc, T beta, T c) {
+#pragma clang fp contract(off)
+    return alpha * acc + beta * c;
+}
+
+// ---------------------------------------------------------------------------
+// Work-group id -> C tile.
+// ---------------------------------------------------------------------------
+// The hardware hands consecutive work-group ids to the 8 XCDs in turn.  First
+// undo that dealing, so that logical ids [x*per, (x+1)*per) all run on XCD x;
+// then walk tiles in groups of GROUP_M tile-rows, column by column, so that a
+// run of consecutive logical ids covers a compact rectangle of C.
+__device__ inline void tile_of_block(int bid, int nblocks, int tiles_m, int tiles_n,
+                                     int &tm, int &tn) {
+    constexpr int XCDS = 8;
+    constexpr int GROUP_M = 8;
+    int full = (nblocks / XCDS) * XCDS;
+    int lid = bid;
+    if (bid < full) {
+        int per = full / XCDS;
+        lid = (bid % XCDS) * per + bid / XCDS;
+    }
+    int group_size = GROUP_M * tiles_n;
+    int group = lid / group_size;
+    int first_m = group * GROUP_M;
+    int gm = tiles_m - first_m < GROUP_M ? tiles_m - first_m : GROUP_M;
+    int in_group = lid - group * group_size;
+    tm = first_m + in_group % gm;
+    tn = in_group / gm;
+}
+
+// ---------------------------------------------------------------------------
+// The kernel.
+// ---------------------------------------------------------------------------
+// T      element type (double or float)
+// BM,BN  C tile of the work-group; BK depth of one k-step
+// WGM,WGN waves along M and N (WGM*WGN waves, 64 lanes each)
+// EPT    consecutive elements one thread copies per run (a multiple of 2)
+// DBUF   two LDS stages (1) or one (0)
+// ALIGN  A and B rows start on 2-element boundaries (even leading dimensions and
+//        aligned base pointers): full runs use 2-element vector loads; otherwise
+//        every element is loaded alone.
+template <typename T, int BM, int BN, int BK, int WGM, int WGN, int EPT, int DBUF, bool ALIGN>
+__global__ void __launch_bounds__(64 * WGM * WGN)
+gemm_tiled_kernel(GemmArgs p) {
+    typedef Elem<T> E;
+    typedef typename E::vec2 vec2;
+    typedef typename E::acc4 acc4;
+    constexpr int NT = 64 * WGM * WGN;
+    constexpr int WM = BM / WGM;           // C rows per wave
+    constexpr int WN = BN / WGN;           // C columns per wave
+    constexpr int FM = WM / 16;            // MFMA fragments per wave along M
+    constexpr int FN = WN / 16;            // ... along N
+    constexpr int SA = BK + 2;             // LDS row stride of the A tile (elements)
+    constexpr int SB = BN + (sizeof(T) == 8 ? 8 : 16);  // LDS row stride of the B tile
+    constexpr int STAGES = DBUF ? 2 : 1;
+    constexpr int A_RUNS = BM * BK / (EPT * NT);   // runs per thread per k-step
+    constexpr int B_RUNS = BK * BN / (EPT * NT);
+    constexpr int A_RUNS_PER_ROW = BK / EPT;
+    constexpr int B_RUNS_PER_ROW = BN / EPT;
+    static_assert(WM % 16 == 0 && WN % 16 == 0, "wave tile must be a multiple of 16");
+    static_assert(BK % 8 == 0, "BK must be a multiple of 8");
+    static_assert(EPT % 2 == 0, "EPT must be even");
+    static_assert(A_RUNS >= 1 && A_RUNS * EPT * NT == BM * BK, "A tile split");
+    static_assert(B_RUNS >= 1 && B_RUNS * EPT * NT == BK * BN, "B tile split");
+    static_assert(A_RUNS_PER_ROW >= 1 && B_RUNS_PER_ROW >= 1, "EPT wider than a tile row");
+
+    __shared__ __attribute__((aligned(16))) T sA[STAGES][BM * SA];
+    __shared__ __attribute__((aligned(16))) T sB[STAGES][BK * SB];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wm = wave / WGN;             // wave position in the work-group grid
+    const int wn = wave % WGN;
+
+    const int tiles_m = (int)((p.m + BM - 1) / BM);
+    const int tiles_n = (int)((p.n + BN - 1) / BN);
+    int tm, tn;
+    tile_of_block(blockIdx.x, gridDim.x, tiles_m, tiles_n, tm, tn);
+    const int64_t m0 = (int64_t)tm * BM;
+    const int64_t n0 = (int64_t)tn * BN;
+
+    const T *__restrict__ A = (const T *)p.A;
+    const T *__restrict__ B = (const T *)p.B;
+    T *__restrict__ C = (T *)p.C;
+    const int64_t lda = p.lda, ldb = p.ldb, ldc = p.ldc;
+    const int64_t mrem = p.m - m0;          // valid rows of this tile (may exceed BM)
+    const int64_t nrem = p.n - n0;
+
+    // Per-thread coordinates of its runs inside the A and B tiles.
+    int a_row[A_RUNS], a_col[A_RUNS];
+#pragma unroll
+    for (int r = 0; r < A_RUNS; ++r) {
+        int run = tid + r * NT;
+        a_row[r] = run / A_RUNS_PER_ROW;
+        a_col[r] = (run % A_RUNS_PER_ROW) * EPT;
+    }
+    int b_row[B_RUNS], b_col[B_RUNS];
+#pragma unroll
+    for (int r = 0; r < B_RUNS; ++r) {
+        int run = tid + r * NT;
+        b_row[r] = run / B_RUNS_PER_ROW;
+        b_col[r] = (run % B_RUNS_PER_ROW) * EPT;
+    }
+
+    vec2 ra[A_RUNS][EPT / 2];
+    vec2 rb[B_RUNS][EPT / 2];
+
+    // Global -> registers for k-step starting at k0 (zero outside the matrix).
+    auto load_tiles = [&](int64_t k0) {
+        const int64_t krem = p.k - k0;
+#pragma unroll
+        for (int r = 0; r < A_RUNS; ++r) {
+            const bool rok = a_row[r] < mrem;
+            const T *src = A + (m0 + a_row[r]) * lda + k0 + a_col[r];
+#pragma unroll
+            for (int v = 0; v < EPT / 2; ++v) {
+                const int c = a_col[r] + 2 * v;
+                vec2 x = {T(0), T(0)};
+                if (rok) {
+                    if (ALIGN && c + 1 < krem) {
+                        x = *(const vec2 *)(src + 2 * v);
+                    } else {
+                        if (c < krem) x[0] = src[2 * v];
+                        if (c + 1 < krem) x[1] = src[2 * v + 1];
+                    }
+                }
+                ra[r][v] = x;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < B_RUNS; ++r) {
+            const bool rok = b_row[r] < krem;
+            const T *src = B + (k0 + b_row[r]) * ldb + n0 + b_col[r];
+#pragma unroll
+            for (int v = 0; v < EPT / 2; ++v) {
+                const int c = b_col[r] + 2 * v;
+                vec2 x = {T(0), T(0)};
+                if (rok) {
+                    if (ALIGN && c + 1 < nrem) {
+                        x = *(const vec2 *)(src + 2 * v);
+                    } else {
+                        if (c < nrem) x[0] = src[2 * v];
+                        if (c + 1 < nrem) x[1] = src[2 * v + 1];
+                    }
+                }
+                rb[r][v] = x;
+            }
+        }
+    };
+
+    auto store_tiles = [&](int st) {
+#pragma unroll
+        for (int r = 0; r < A_RUNS; ++r)
+#pragma unroll
+            for (int v = 0; v < EPT / 2; ++v)
+                *(vec2 *)&sA[st][a_row[r] * SA + a_col[r] + 2 * v] = ra[r][v];
+#pragma unroll
+        for (int r = 0; r < B_RUNS; ++r)
+#pragma unroll
+            for (int v = 0; v < EPT / 2; ++v)
+                *(vec2 *)&sB[st][b_row[r] * SB + b_col[r] + 2 * v] = rb[r][v];
+    };
+
+    acc4 acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) acc[i][j] = acc4{0, 0, 0, 0};
+
+    const int l16 = lane & 15;     // row of A / column of B inside a fragment
+    const int kq = lane >> 4;      // which pair of k values this lane feeds
+    const int a_base = (wm * WM + l16) * SA + 2 * kq;
+    const int b_base = (2 * kq) * SB + wn * WN + l16;
+
+    auto multiply = [&](int st) {
+        const T *tA = sA[st];
+        const T *tB = sB[st];
+#pragma unroll
+        for (int g = 0; g < BK / 8; ++g) {
+            vec2 af[FM];
+            T bf0[FN], bf1[FN];
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+                af[i] = *(const vec2 *)&tA[a_base + i * 16 * SA + g * 8];
+#pragma unroll
+            for (int j = 0; j < FN; ++j) {
+                bf0[j] = tB[b_base + (g * 8) * SB + j * 16];
+                bf1[j] = tB[b_base + (g * 8 + 1) * SB + j * 16];
+            }
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j) {
+                    acc[i][j] = E::mma(af[i][0], bf0[j], acc[i][j]);
+                    acc[i][j] = E::mma(af[i][1], bf1[j], acc[i][j]);
+                }
+        }
+    };
+
+    const int64_t nk = (p.k + BK - 1) / BK;
+    load_tiles(0);
+    store_tiles(0);
+    __syncthreads();
+    for (int64_t kt = 0; kt < nk; ++kt) {
+        const int cur = DBUF ? (int)(kt & 1) : 0;
+        const bool more = kt + 1 < nk;
+        if (more) load_tiles((kt + 1) * BK);
+        multiply(cur);
+        if (more) {
+            if (!DBUF) __syncthreads();
+            store_tiles(DBUF ? cur ^ 1 : 0);
+        }
+        __syncthreads();
+    }
+
+    // Epilogue: lane holds rows 4*kq + 0..3 and column l16 of each fragment.
+    const T alpha = (T)p.alpha;
+    const T beta = (T)p.beta;
+    const bool read_c = p.beta != 0.0;
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+            const int64_t col = wn * WN + j * 16 + l16;
+            if (col >= nrem) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t row = wm * WM + i * 16 + 4 * kq + r;
+                if (row >= mrem) continue;
+                T *c = C + (m0 + row) * ldc + n0 + col;
+                *c = read_c ? scale_add(alpha, acc[i][j][r], beta, *c) : alpha * acc[i][j][r];
+            }
+        }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers and registries.
+// ---------------------------------------------------------------------------
+template <typename T, int BM, int BN, int BK, int WGM, int WGN, int EPT, int DBUF, bool ALIGN>
+hipError_t launch_tiled(const GemmArgs &a, hipStream_t s) {
+    int64_t blocks = ((a.m + BM - 1) / BM) * ((a.n + BN - 1) / BN);
+    if (blocks <= 0) return hipSuccess;
+    if (blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL((gemm_tiled_kernel<T, BM, BN, BK, WGM, WGN, EPT, DBUF, ALIGN>),
+                       dim3((unsigned)blocks), dim3(64 * WGM * WGN), 0, s, a);
+    return hipGetLastError();
+}
+
+#define MGEMM_CFG(T, BM, BN, BK, WGM, WGN, EPT, DBUF)                                   \
+    {{BM, BN, BK, WGM * WGN, EPT, DBUF},                                                  \
+     &launch_tiled<T, BM, BN, BK, WGM, WGN, EPT, DBUF, true>,                             \
+     &launch_tiled<T, BM, BN, BK, WGM, WGN, EPT, DBUF, false>}
+
+static const KernelEntry kF64[] = {
+    MGEMM_CFG(double, 128, 128, 16, 2, 2, 2, 1),
+    MGEMM_CFG(double, 64, 64, 16, 2, 2, 2, 1),
+    MGEMM_CFG(double, 128, 64, 16, 2, 2, 2, 1),
+    MGEMM_CFG(double, 128, 128, 32, 2, 2, 4, 1),
+    MGEMM_CFG(double, 256, 128, 16, 4, 2, 2, 1),
+    MGEMM_CFG(double, 32, 32, 16, 1, 1, 2, 1),
+};
+
+static const KernelEntry kF32[] = {
+    MGEMM_CFG(float, 128, 128, 16, 2, 2, 2, 1),
+    MGEMM_CFG(float, 64, 64, 16, 2, 2, 2, 1),
+    MGEMM_CFG(float, 128, 128, 32, 2, 2, 4, 1),
+    MGEMM_CFG(float, 32, 32, 16, 1, 1, 2, 1),
+};
+
+const KernelEntry *f64_registry(int *count) {
+    *count = (int)(sizeof(kF64) / sizeof(kF64[0]));
+    return kF64;
+}
+
+const KernelEntry *f32_registry(int *count) {
+    *count = (int)(sizeof(kF32) / sizeof(kF32[0]));
+    return kF32;
+}
+
+}  // namespace mgemm

@@ -1,0 +1,207 @@
+// The C ABI of the library: argument checks, configuration choice and dispatch.
+//
+// Argument numbering and the -i convention follow the prototypes in mgemm.h:
+// m=1 n=2 k=3 alpha=4 A=5 lda=6 B=7 ldb=8 beta=9 C=10 ldc=11 dtype=12 cfg=13
+// stream=14.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <mutex>
+#include <string>
+
+#include "mgemm_internal.h"
+
+namespace mgemm {
+
+static thread_local std::string g_err;
+static hipStream_t g_stream = nullptr;
+
+int32_t set_error(int32_t code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+static int32_t hip_error(hipError_t e, const char *where) {
+    return set_error(MGEMM_ERR_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+static size_t elem_size(int32_t dtype) {
+    return dtype == MGEMM_F32 ? 4 : 8;
+}
+
+static bool ranges_overlap(const void *p, size_t pbytes, const void *q, size_t qbytes) {
+    uintptr_t a = (uintptr_t)p, b = (uintptr_t)q;
+    return a < b + qbytes && b < a + pbytes;
+}
+
+// Bytes spanned by an r x c row-major matrix with leading dimension ld.
+static size_t span_bytes(int64_t r, int64_t c, int64_t ld, size_t es) {
+    if (r <= 0 || c <= 0) return 0;
+    return (size_t)((r - 1) * ld + c) * es;
+}
+
+// Checks the arguments in position order; returns 0 or -i.
+int32_t check_args(int64_t m, int64_t n, int64_t k, double alpha, const void *A, int64_t lda,
+                   const void *B, int64_t ldb, const void *C, int64_t ldc, int32_t dtype) {
+    if (m < 0) return set_error(-1, "m < 0");
+    if (n < 0) return set_error(-2, "n < 0");
+    if (k < 0) return set_error(-3, "k < 0");
+    const bool reads_ab = m > 0 && n > 0 && k > 0 && alpha != 0.0;
+    if (reads_ab && A == nullptr) return set_error(-5, "A is NULL");
+    if (lda < (k > 1 ? k : 1)) return set_error(-6, "lda < max(1,k)");
+    if (reads_ab && B == nullptr) return set_error(-7, "B is NULL");
+    if (ldb < (n > 1 ? n : 1)) return set_error(-8, "ldb < max(1,n)");
+    if (m > 0 && n > 0 && C == nullptr) return set_error(-10, "C is NULL");
+    if (ldc < (n > 1 ? n : 1)) return set_error(-11, "ldc < max(1,n)");
+    if (dtype < MGEMM_F64 || dtype > MGEMM_SPLIT_FP8) return set_error(-12, "unknown dtype %d", dtype);
+    if (reads_ab) {
+        const size_t es = elem_size(dtype);
+        const size_t cb = span_bytes(m, n, ldc, es);
+        if (ranges_overlap(C, cb, A, span_bytes(m, k, lda, es)) ||
+            ranges_overlap(C, cb, B, span_bytes(k, n, ldb, es)))
+            return set_error(-10, "C overlaps A or B");
+    }
+    return 0;
+}
+
+// C = beta*C (k == 0 or alpha == 0); beta == 0 writes zeros without reading C.
+template <typename T>
+__global__ void scale_c_kernel(T *C, int64_t m, int64_t n, int64_t ldc, T beta) {
+    int64_t total = m * n;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        int64_t i = idx / n, j = idx - i * n;
+        T *c = C + i * ldc + j;
+        *c = beta == T(0) ? T(0) : beta * *c;
+    }
+}
+
+static int32_t scale_c(int32_t dtype, int64_t m, int64_t n, double beta, void *C, int64_t ldc,
+                       hipStream_t s) {
+    if (beta == 1.0) return 0;
+    int64_t total = m * n;
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    if (dtype == MGEMM_F32)
+        hipLaunchKernelGGL(scale_c_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, s,
+                           (float *)C, m, n, ldc, (float)beta);
+    else
+        hipLaunchKernelGGL(scale_c_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, s,
+                           (double *)C, m, n, ldc, beta);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? 0 : hip_error(e, "scale_c launch");
+}
+
+static const KernelEntry *registry(int32_t dtype, int *count) {
+    switch (dtype) {
+    case MGEMM_F64: return f64_registry(count);
+    case MGEMM_F32: return f32_registry(count);
+    default: *count = 0; return nullptr;
+    }
+}
+
+static bool same_cfg(const mgemm_cfg &a, const mgemm_cfg &b) {
+    return a.bm == b.bm && a.bn == b.bn && a.bk == b.bk && a.waves == b.waves &&
+           a.elems_per_thread == b.elems_per_thread && a.double_buffer == b.double_buffer;
+}
+
+// Built-in choice when no configuration is given: the largest tile that still
+// gives every compute unit work, else the smallest tile.
+static const KernelEntry *default_entry(const KernelEntry *reg, int cnt, int64_t m, int64_t n) {
+    static const int kOrder[][3] = {{128, 128, 16}, {128, 64, 16}, {64, 64, 16}, {32, 32, 16}};
+    for (auto &o : kOrder) {
+        for (int i = 0; i < cnt; ++i) {
+            const mgemm_cfg &c = reg[i].cfg;
+            if (c.bm == o[0] && c.bn == o[1] && c.bk == o[2]) {
+                if (tiles_of(m, n, c) >= 256 || o[0] == 32) return &reg[i];
+            }
+        }
+    }
+    return cnt > 0 ? &reg[0] : nullptr;
+}
+
+static bool aligned_rows(const void *p, int64_t ld, size_t es) {
+    return ((uintptr_t)p % (2 * es)) == 0 && (ld % 2) == 0;
+}
+
+int32_t split_gemm(const GemmArgs &a, int32_t dtype, hipStream_t s);
+
+}  // namespace mgemm
+
+using namespace mgemm;
+
+extern "C" {
+
+int32_t gemm_ex(int64_t m, int64_t n, int64_t k, double alpha, const void *A, int64_t lda,
+                const void *B, int64_t ldb, double beta, void *C, int64_t ldc, int32_t dtype,
+                const mgemm_cfg *cfg, void *stream) {
+    g_err.clear();
+    int32_t rc = check_args(m, n, k, alpha, A, lda, B, ldb, C, ldc, dtype);
+    if (rc) return rc;
+    hipStream_t s = stream ? (hipStream_t)stream : g_stream;
+    if (m == 0 || n == 0) return 0;
+    if (k == 0 || alpha == 0.0) {
+        return scale_c(dtype == MGEMM_F32 ? MGEMM_F32 : MGEMM_F64, m, n, beta, C, ldc, s);
+    }
+    GemmArgs a{m, n, k, alpha, beta, A, lda, B, ldb, C, ldc};
+    if (dtype == MGEMM_SPLIT_BF16 || dtype == MGEMM_SPLIT_FP8) {
+        if (cfg) return set_error(-13, "split dtypes take no tile configuration");
+        return split_gemm(a, dtype, s);
+    }
+    int cnt = 0;
+    const KernelEntry *reg = registry(dtype, &cnt);
+    const KernelEntry *e = nullptr;
+    if (cfg) {
+        for (int i = 0; i < cnt; ++i)
+            if (same_cfg(reg[i].cfg, *cfg)) { e = &reg[i]; break; }
+        if (!e)
+            return set_error(-13, "configuration %dx%dx%d w%d e%d d%d is not registered",
+                             cfg->bm, cfg->bn, cfg->bk, cfg->waves, cfg->elems_per_thread,
+                             cfg->double_buffer);
+    } else {
+        e = default_entry(reg, cnt, m, n);
+        if (!e) return set_error(MGEMM_ERR_NOCONFIG, "no configuration for dtype %d", dtype);
+    }
+    const size_t es = elem_size(dtype);
+    const bool al = aligned_rows(A, lda, es) && aligned_rows(B, ldb, es);
+    hipError_t he = (al ? e->launch : e->launch_unaligned)(a, s);
+    if (he != hipSuccess) return hip_error(he, "gemm launch");
+    return 0;
+}
+
+int32_t gemm(int64_t m, int64_t n, int64_t k, double alpha, const void *A, int64_t lda,
+             const void *B, int64_t ldb, double beta, void *C, int64_t ldc, int32_t dtype) {
+    return gemm_ex(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, dtype, nullptr, nullptr);
+}
+
+int32_t mgemm_set_stream(void *stream) {
+    g_stream = (hipStream_t)stream;
+    return 0;
+}
+
+const char *mgemm_last_error(void) { return g_err.c_str(); }
+
+int32_t mgemm_config_count(int32_t dtype) {
+    if (dtype < MGEMM_F64 || dtype > MGEMM_SPLIT_FP8) return -1;
+    int cnt = 0;
+    registry(dtype, &cnt);
+    return cnt;
+}
+
+int32_t mgemm_config_get(int32_t dtype, int32_t i, mgemm_cfg *out) {
+    if (dtype < MGEMM_F64 || dtype > MGEMM_SPLIT_FP8) return -1;
+    int cnt = 0;
+    const KernelEntry *reg = registry(dtype, &cnt);
+    if (i < 0 || i >= cnt) return -2;
+    if (!out) return -3;
+    *out = reg[i].cfg;
+    return 0;
+}
+
+}  // extern "C"

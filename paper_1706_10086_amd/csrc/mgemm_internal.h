@@ -1,0 +1,43 @@
+// Internal declarations shared by the HIP kernel files and the C-ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mgemm.h"
+
+namespace mgemm {
+
+// Arguments of one GEMM, already validated on the host.
+struct GemmArgs {
+    int64_t m, n, k;
+    double alpha, beta;
+    const void *A;
+    int64_t lda;
+    const void *B;
+    int64_t ldb;
+    void *C;
+    int64_t ldc;
+};
+
+// A registered kernel: its configuration and its launcher.
+typedef hipError_t (*LaunchFn)(const GemmArgs &, hipStream_t);
+
+struct KernelEntry {
+    mgemm_cfg cfg;
+    LaunchFn launch;
+    // true when the kernel needs 16-byte aligned A/B rows (even leading dims and
+    // aligned base pointers for 8-byte elements)
+    LaunchFn launch_unaligned;
+};
+
+// Per-dtype registries, defined in the kernel files.
+const KernelEntry *f64_registry(int *count);
+const KernelEntry *f32_registry(int *count);
+
+// Number of work-groups a configuration launches for an m x n output.
+inline int64_t tiles_of(int64_t m, int64_t n, const mgemm_cfg &c) {
+    return ((m + c.bm - 1) / c.bm) * ((n + c.bn - 1) / c.bn);
+}
+
+}  // namespace mgemm

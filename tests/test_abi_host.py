@@ -1,0 +1,87 @@
+"""Host-side checks of the C-ABI library that need no GPU: it loads, exports every
+symbol include/mgemm.h declares, and rejects invalid arguments with the -i code of
+the first bad argument (BLAS convention) before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1706_10086_amd as mg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_symbols():
+    text = open(os.path.join(ROOT, "include", "mgemm.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return set(re.findall(r"^\s*(?:MGEMM_API\s+)?(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", text, flags=re.M))
+
+
+@pytest.fixture(scope="module")
+def L():
+    try:
+        return mg.lib()
+    except mg.MgemmNotBuilt:
+        pytest.skip("libmgemm.so not built")
+
+
+def test_every_declared_symbol_is_exported(L):
+    syms = header_symbols()
+    assert {"gemm", "gemm_ex", "mgemm_last_error"} <= syms
+    for s in syms:
+        assert hasattr(L, s), s
+    assert set(mg.EXPORTED) == syms
+
+
+P = 1 << 20   # a fake, never dereferenced device address
+
+
+@pytest.mark.parametrize("args,code", [
+    ((-1, 4, 4, 1.0, P, 4, P, 4, 0.0, P * 2, 4, 0), -1),
+    ((4, -1, 4, 1.0, P, 4, P, 4, 0.0, P * 2, 4, 0), -2),
+    ((4, 4, -1, 1.0, P, 4, P, 4, 0.0, P * 2, 4, 0), -3),
+    ((4, 4, 4, 1.0, 0, 4, P, 4, 0.0, P * 2, 4, 0), -5),
+    ((4, 4, 8, 1.0, P, 7, P, 4, 0.0, P * 2, 4, 0), -6),
+    ((4, 4, 4, 1.0, P, 4, 0, 4, 0.0, P * 2, 4, 0), -7),
+    ((4, 5, 4, 1.0, P, 4, P * 4, 4, 0.0, P * 2, 5, 0), -8),
+    ((4, 4, 4, 1.0, P, 4, P * 4, 4, 0.0, 0, 4, 0), -10),
+    ((4, 5, 4, 1.0, P, 4, P * 4, 5, 0.0, P * 2, 4, 0), -11),
+    ((4, 4, 4, 1.0, P, 4, P * 4, 4, 0.0, P * 2, 4, 7), -12),
+    ((4, 4, 4, 1.0, P, 4, P * 4, 4, 0.0, P * 2, 4, -1), -12),
+    # C overlapping A
+    ((4, 4, 4, 1.0, P, 4, P * 4, 4, 0.0, P + 64, 4, 0), -10),
+    # the first bad argument wins
+    ((-1, -1, 4, 1.0, 0, 0, 0, 0, 0.0, 0, 0, 9), -1),
+    ((4, 4, 4, 1.0, 0, 1, 0, 1, 0.0, 0, 1, 9), -5),
+])
+def test_invalid_arguments(L, args, code):
+    assert mg.gemm_raw(*args) == code
+    assert mg.last_error() != ""
+
+
+def test_empty_problems_return_without_device_work(L):
+    # m == 0 or n == 0: nothing to do, NULL pointers allowed
+    assert mg.gemm_raw(0, 4, 4, 1.0, 0, 4, 0, 4, 0.0, 0, 4, 0) == 0
+    assert mg.gemm_raw(4, 0, 4, 1.0, 0, 4, 0, 1, 0.0, 0, 1, 1) == 0
+    # lda >= max(1, k) also when k == 0
+    assert mg.gemm_raw(0, 0, 0, 1.0, 0, 1, 0, 1, 0.0, 0, 1, 0) == 0
+    assert mg.gemm_raw(0, 0, 0, 1.0, 0, 0, 0, 1, 0.0, 0, 1, 0) == -6
+
+
+def test_unregistered_config_rejected(L):
+    bad = mg.Cfg(48, 48, 16, 4, 2, 1)
+    assert mg.gemm_ex_raw(4, 4, 4, 1.0, P, 4, P * 4, 4, 0.0, P * 2, 4, 0, bad, None) == -13
+
+
+def test_config_registry(L):
+    for dt in (mg.F64, mg.F32):
+        cs = mg.configs(dt)
+        assert len(cs) >= 1
+        for c in cs:
+            assert c.bm % 16 == 0 and c.bn % 16 == 0 and c.bk % 8 == 0
+            assert c.waves in (1, 2, 4, 8) and c.double_buffer in (0, 1)
+        assert len({c.as_tuple() for c in cs}) == len(cs)
+    assert L.mgemm_config_count(9) < 0
+    c = mg.Cfg()
+    assert L.mgemm_config_get(mg.F64, 10 ** 6, ctypes.byref(c)) == -2
