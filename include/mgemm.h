@@ -114,7 +114,8 @@ MGEMM_API int32_t mgemm_release_workspace(void);
 
 /* Diagnostic: one matrix-core step on one wave with the fragment layout the
  * tiled kernels assume (lane l supplies A[l%16][l/16] and B[l/16][l%16] and
- * receives D[4*(l/16)+r][l%16] in accumulator element r).  dtype is MGEMM_F64 or
+ * receives column l%16 of D; with q = l/16, accumulator element r holds row
+ * q+4r for FP64 and row 4q+r for FP32).  dtype is MGEMM_F64 or
  * MGEMM_F32; A (16x4), B (4x16) and D (16x16) are row-major device buffers; on
  * a correct layout D = A*B.  Returns 0, -1 (dtype) or -2 (NULL buffer). */
 MGEMM_API int32_t mgemm_probe_mfma(int32_t dtype, const void *A, const void *B, void *D,

@@ -44,6 +44,9 @@ template <> struct Elem<double> {
     __device__ static inline acc4 mma(double a, double b, acc4 c) {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
+    // Row of D held in accumulator element r by lanes 16q..16q+15 (column l%16):
+    // the FP64 instruction interleaves rows q, q+4, q+8, q+12.
+    __device__ static inline int out_row(int q, int r) { return q + 4 * r; }
 };
 
 template <> struct Elem<float> {
@@ -52,6 +55,8 @@ template <> struct Elem<float> {
     __device__ static inline acc4 mma(float a, float b, acc4 c) {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
+    // The FP32 instruction gives lanes 16q..16q+15 the four rows 4q..4q+3.
+    __device__ static inline int out_row(int q, int r) { return 4 * q + r; }
 };
 
 // alpha*acc + beta*c with each product and the sum rounded separately (no
@@ -274,7 +279,7 @@ gemm_tiled_kernel(GemmArgs p) {
         __syncthreads();
     }
 
-    // Epilogue: lane holds rows 4*kq + 0..3 and column l16 of each fragment.
+    // Epilogue: lane holds column l16 and rows E::out_row(kq, 0..3) of each fragment.
     const T alpha = (T)p.alpha;
     const T beta = (T)p.beta;
     const bool read_c = p.beta != 0.0;
@@ -286,7 +291,7 @@ gemm_tiled_kernel(GemmArgs p) {
             if (col >= nrem) continue;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int64_t row = wm * WM + i * 16 + 4 * kq + r;
+                const int64_t row = wm * WM + i * 16 + E::out_row(kq, r);
                 if (row >= mrem) continue;
                 T *c = C + (m0 + row) * ldc + n0 + col;
                 *c = read_c ? scale_add(alpha, acc[i][j][r], beta, *c) : alpha * acc[i][j][r];

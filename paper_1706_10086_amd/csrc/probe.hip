@@ -1,6 +1,7 @@
 // One matrix-core step on a single wave, for checking the fragment layout that
 // the tiled kernels assume: lane l supplies A[l%16][l/16] and B[l/16][l%16] and
-// receives D[4*(l/16) + r][l%16] in accumulator element r.
+// receives column l%16 of D; with q = l/16, accumulator element r holds row
+// q + 4r for FP64 and row 4q + r for FP32.
 #include "mgemm_internal.h"
 
 namespace mgemm {
@@ -13,7 +14,7 @@ __global__ void probe_f64(const double *A, const double *B, double *D) {
     v4d acc = {0, 0, 0, 0};
     acc = __builtin_amdgcn_mfma_f64_16x16x4f64(A[(l % 16) * 4 + l / 16], B[(l / 16) * 16 + l % 16],
                                                acc, 0, 0, 0);
-    for (int r = 0; r < 4; ++r) D[(4 * (l / 16) + r) * 16 + l % 16] = acc[r];
+    for (int r = 0; r < 4; ++r) D[(l / 16 + 4 * r) * 16 + l % 16] = acc[r];
 }
 
 __global__ void probe_f32(const float *A, const float *B, float *D) {
