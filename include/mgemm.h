@@ -75,9 +75,12 @@ enum {
  *                     load (the paper's element layer).
  *   double_buffer     1: two LDS stages, the next k-step's tiles are loaded while
  *                     the current one is multiplied; 0: one stage.
+ *   occupancy         wavefronts per SIMD the kernel is compiled to allow (0: the
+ *                     compiler's choice, else 1 or 2) -- the GPU counterpart of
+ *                     the paper's hardware threads per core (Sec. 3, Tab. 4).
  */
 typedef struct {
-    int32_t bm, bn, bk, waves, elems_per_thread, double_buffer;
+    int32_t bm, bn, bk, waves, elems_per_thread, double_buffer, occupancy;
 } mgemm_cfg;
 
 /* C = alpha*A*B + beta*C (Eq. 1) with the library's choice of tile configuration,

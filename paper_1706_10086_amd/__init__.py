@@ -44,13 +44,17 @@ class MgemmError(RuntimeError):
 class Cfg(ctypes.Structure):
     _fields_ = [("bm", ctypes.c_int32), ("bn", ctypes.c_int32), ("bk", ctypes.c_int32),
                 ("waves", ctypes.c_int32), ("elems_per_thread", ctypes.c_int32),
-                ("double_buffer", ctypes.c_int32)]
+                ("double_buffer", ctypes.c_int32), ("occupancy", ctypes.c_int32)]
 
     def as_tuple(self):
-        return (self.bm, self.bn, self.bk, self.waves, self.elems_per_thread, self.double_buffer)
+        return (self.bm, self.bn, self.bk, self.waves, self.elems_per_thread, self.double_buffer,
+                self.occupancy)
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
     def __repr__(self):
-        return "Cfg(%d,%d,%d,w%d,e%d,d%d)" % self.as_tuple()
+        return "Cfg(%d,%d,%d,w%d,e%d,d%d,o%d)" % self.as_tuple()
 
 
 _lib = None

@@ -101,11 +101,14 @@ __device__ inline void tile_of_block(int bid, int nblocks, int tiles_m, int tile
 // WGM,WGN waves along M and N (WGM*WGN waves, 64 lanes each)
 // EPT    consecutive elements one thread copies per run (a multiple of 2)
 // DBUF   two LDS stages (1) or one (0)
+// OCC    minimum waves per SIMD the register allocation must allow (0: no limit)
 // ALIGN  A and B rows start on 2-element boundaries (even leading dimensions and
 //        aligned base pointers): full runs use 2-element vector loads; otherwise
 //        every element is loaded alone.
-template <typename T, int BM, int BN, int BK, int WGM, int WGN, int EPT, int DBUF, bool ALIGN>
+template <typename T, int BM, int BN, int BK, int WGM, int WGN, int EPT, int DBUF, int OCC,
+          bool ALIGN>
 __global__ void __launch_bounds__(64 * WGM * WGN)
+__attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1)))
 gemm_tiled_kernel(GemmArgs p) {
     typedef Elem<T> E;
     typedef typename E::vec2 vec2;
@@ -302,35 +305,45 @@ gemm_tiled_kernel(GemmArgs p) {
 // ---------------------------------------------------------------------------
 // Launchers and registries.
 // ---------------------------------------------------------------------------
-template <typename T, int BM, int BN, int BK, int WGM, int WGN, int EPT, int DBUF, bool ALIGN>
+template <typename T, int BM, int BN, int BK, int WGM, int WGN, int EPT, int DBUF, int OCC,
+          bool ALIGN>
 hipError_t launch_tiled(const GemmArgs &a, hipStream_t s) {
     int64_t blocks = ((a.m + BM - 1) / BM) * ((a.n + BN - 1) / BN);
     if (blocks <= 0) return hipSuccess;
     if (blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((gemm_tiled_kernel<T, BM, BN, BK, WGM, WGN, EPT, DBUF, ALIGN>),
+    hipLaunchKernelGGL((gemm_tiled_kernel<T, BM, BN, BK, WGM, WGN, EPT, DBUF, OCC, ALIGN>),
                        dim3((unsigned)blocks), dim3(64 * WGM * WGN), 0, s, a);
     return hipGetLastError();
 }
 
-#define MGEMM_CFG(T, BM, BN, BK, WGM, WGN, EPT, DBUF)                                   \
-    {{BM, BN, BK, WGM * WGN, EPT, DBUF},                                                  \
-     &launch_tiled<T, BM, BN, BK, WGM, WGN, EPT, DBUF, true>,                             \
-     &launch_tiled<T, BM, BN, BK, WGM, WGN, EPT, DBUF, false>}
+#define MGEMM_CFG(T, BM, BN, BK, WGM, WGN, EPT, DBUF, OCC)                              \
+    {{BM, BN, BK, WGM * WGN, EPT, DBUF, OCC},                                             \
+     &launch_tiled<T, BM, BN, BK, WGM, WGN, EPT, DBUF, OCC, true>,                        \
+     &launch_tiled<T, BM, BN, BK, WGM, WGN, EPT, DBUF, OCC, false>}
 
 static const KernelEntry kF64[] = {
-    MGEMM_CFG(double, 128, 128, 16, 2, 2, 2, 1),
-    MGEMM_CFG(double, 64, 64, 16, 2, 2, 2, 1),
-    MGEMM_CFG(double, 128, 64, 16, 2, 2, 2, 1),
-    MGEMM_CFG(double, 128, 128, 32, 2, 2, 4, 1),
-    MGEMM_CFG(double, 256, 128, 16, 4, 2, 2, 1),
-    MGEMM_CFG(double, 32, 32, 16, 1, 1, 2, 1),
+    MGEMM_CFG(double, 128, 128, 16, 2, 2, 2, 1, 0),
+    MGEMM_CFG(double, 128, 128, 16, 2, 2, 2, 1, 2),
+    MGEMM_CFG(double, 128, 128, 16, 2, 2, 2, 0, 2),
+    MGEMM_CFG(double, 128, 128, 32, 2, 2, 4, 1, 0),
+    MGEMM_CFG(double, 256, 128, 16, 4, 2, 2, 1, 0),
+    MGEMM_CFG(double, 128, 256, 16, 2, 4, 2, 1, 0),
+    MGEMM_CFG(double, 128, 64, 16, 2, 2, 2, 1, 0),
+    MGEMM_CFG(double, 128, 64, 32, 2, 2, 4, 0, 2),
+    MGEMM_CFG(double, 64, 64, 16, 2, 2, 2, 1, 0),
+    MGEMM_CFG(double, 64, 64, 32, 2, 2, 2, 1, 0),
+    MGEMM_CFG(double, 32, 32, 16, 1, 1, 2, 1, 0),
 };
 
 static const KernelEntry kF32[] = {
-    MGEMM_CFG(float, 128, 128, 16, 2, 2, 2, 1),
-    MGEMM_CFG(float, 64, 64, 16, 2, 2, 2, 1),
-    MGEMM_CFG(float, 128, 128, 32, 2, 2, 4, 1),
-    MGEMM_CFG(float, 32, 32, 16, 1, 1, 2, 1),
+    MGEMM_CFG(float, 128, 128, 16, 2, 2, 2, 1, 0),
+    MGEMM_CFG(float, 128, 128, 32, 2, 2, 4, 1, 0),
+    MGEMM_CFG(float, 128, 128, 32, 2, 2, 4, 1, 2),
+    MGEMM_CFG(float, 256, 128, 32, 4, 2, 4, 1, 0),
+    MGEMM_CFG(float, 128, 256, 32, 2, 4, 4, 1, 0),
+    MGEMM_CFG(float, 128, 64, 32, 2, 2, 4, 1, 0),
+    MGEMM_CFG(float, 64, 64, 16, 2, 2, 2, 1, 0),
+    MGEMM_CFG(float, 32, 32, 16, 1, 1, 2, 1, 0),
 };
 
 const KernelEntry *f64_registry(int *count) {

@@ -108,7 +108,8 @@ static const KernelEntry *registry(int32_t dtype, int *count) {
 
 static bool same_cfg(const mgemm_cfg &a, const mgemm_cfg &b) {
     return a.bm == b.bm && a.bn == b.bn && a.bk == b.bk && a.waves == b.waves &&
-           a.elems_per_thread == b.elems_per_thread && a.double_buffer == b.double_buffer;
+           a.elems_per_thread == b.elems_per_thread && a.double_buffer == b.double_buffer &&
+           a.occupancy == b.occupancy;
 }
 
 // Built-in choice when no configuration is given: the largest tile that still
@@ -161,9 +162,9 @@ int32_t gemm_ex(int64_t m, int64_t n, int64_t k, double alpha, const void *A, in
         for (int i = 0; i < cnt; ++i)
             if (same_cfg(reg[i].cfg, *cfg)) { e = &reg[i]; break; }
         if (!e)
-            return set_error(-13, "configuration %dx%dx%d w%d e%d d%d is not registered",
+            return set_error(-13, "configuration %dx%dx%d w%d e%d d%d o%d is not registered",
                              cfg->bm, cfg->bn, cfg->bk, cfg->waves, cfg->elems_per_thread,
-                             cfg->double_buffer);
+                             cfg->double_buffer, cfg->occupancy);
     } else {
         e = default_entry(reg, cnt, m, n);
         if (!e) return set_error(MGEMM_ERR_NOCONFIG, "no configuration for dtype %d", dtype);

@@ -70,7 +70,7 @@ def test_empty_problems_return_without_device_work(L):
 
 
 def test_unregistered_config_rejected(L):
-    bad = mg.Cfg(48, 48, 16, 4, 2, 1)
+    bad = mg.Cfg(48, 48, 16, 4, 2, 1, 0)
     assert mg.gemm_ex_raw(4, 4, 4, 1.0, P, 4, P * 4, 4, 0.0, P * 2, 4, 0, bad, None) == -13
 
 
@@ -80,7 +80,7 @@ def test_config_registry(L):
         assert len(cs) >= 1
         for c in cs:
             assert c.bm % 16 == 0 and c.bn % 16 == 0 and c.bk % 8 == 0
-            assert c.waves in (1, 2, 4, 8) and c.double_buffer in (0, 1)
+            assert c.waves in (1, 2, 4, 8) and c.double_buffer in (0, 1) and c.occupancy in (0, 1, 2)
         assert len({c.as_tuple() for c in cs}) == len(cs)
     assert L.mgemm_config_count(9) < 0
     c = mg.Cfg()
