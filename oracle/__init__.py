@@ -33,7 +33,8 @@ CFLAGS = ["-O2", "-mavx2", "-mfma", "-ffp-contract=off", "-fno-fast-math",
 
 FMT_BF16 = 0
 FMT_E4M3 = 1
-DEFAULT_SLICES = {FMT_BF16: 6, FMT_E4M3: 11}
+FMT_INT8 = 2
+DEFAULT_SLICES = {FMT_BF16: 6, FMT_E4M3: 11, FMT_INT8: 8}
 ERR_NONFINITE = 3
 
 
@@ -144,6 +145,8 @@ def split_gemm(alpha, A, B, beta=0.0, C=None, fmt: int = FMT_BF16, S: int | None
                               float(beta), _ptr(C), max(1, n), fmt, S, int(nthreads))
     if rc == ERR_NONFINITE:
         raise FloatingPointError("non-finite input")
+    if rc == -14:
+        raise OverflowError("k too large for the exact level sum")
     if rc != 0:
         raise ValueError(f"split_gemm status {rc}")
     return C

@@ -27,7 +27,7 @@
  *   orc_split_*     -- the split-precision (Ozaki-style) emulation of an FP64 GEMM:
  *                      exact power-of-two scaling per row of A and column of B, exact
  *                      slicing into small integers, exact integer slice-pair
- *                      products, FP64 recombination (Ozaki, Ogita, Oishi, Rump,
+ *                      products, one rounding to FP64 (Ozaki, Ogita, Oishi, Rump,
  *                      "Error-free transformations of matrix multiplication ...",
  *                      Numer. Algorithms 59, 2012).
  *   orc_mlp_*       -- FP64 forward/backward/Adam of the 3-layer MLP cost model.
@@ -163,21 +163,24 @@ void orc_gemm_dot2(int64_t m, int64_t n, int64_t k, double alpha,
 /* Split-precision emulation of FP64 GEMM (Ozaki scheme)                      */
 /* ------------------------------------------------------------------------- */
 /*
- * Slice format.  fmt 0: bfloat16 pieces, every integer |q| <= D = 2^8 is exact;
- * fmt 1: FP8 e4m3 pieces, every integer |q| <= D = 2^4 is exact.  The first piece
- * carries b1 = log2(D) bits, each later piece b = b1 + 1 bits (the remainder left by
- * round-to-nearest is at most one half, so one more bit fits under D).
+ * Slice formats (fmt):
+ *   0  bfloat16 pieces: every integer |q| <= 2^8 is exact.  First piece b1 = 8
+ *      bits, later pieces b = 9 bits, rounding to nearest (the remainder left by
+ *      round-to-nearest is at most one half, so one more bit fits under 2^8).
+ *   1  FP8 e4m3 pieces: integers |q| <= 2^4 exact; b1 = 4, b = 5, nearest.
+ *   2  int8 pieces: integers |q| <= 127; b1 = b = 7 bits, rounding toward zero
+ *      (|x| < 2^7 keeps |trunc(x)| <= 127 and leaves a remainder in (-1, 1)).
  *
  * Step 1 (scale, exact): e_i is the exponent with 2^(e_i-1) <= max_p |A_ip| < 2^e_i
  *   (0 for an all-zero row); f_j likewise over column j of B.
- * Step 2 (slice, exact): x = A_ip * 2^(b1 - e_i); q_1 = rint(x); r = x - q_1;
- *   for s >= 2: x = r * 2^b; q_s = rint(x); r = x - q_s.
+ * Step 2 (slice, exact): x = A_ip * 2^(b1 - e_i); q_1 = round(x); r = x - q_1;
+ *   for s >= 2: x = r * 2^b; q_s = round(x); r = x - q_s.
  *   Then A_ip = 2^e_i * ( sum_s q_s 2^-(b1 + b(s-1)) + r_S 2^-(b1 + b(S-1)) ).
  * Step 3 (products, exact): G^(s,t) = Q_A^(s) Q_B^(t) in integer arithmetic, for the
  *   pairs with s + t <= S + 1.
- * Step 4 (recombine, FP64): level L = s + t has unit 2^-(2 b1 + b (L-2)); the level
- *   sums (exact integers) are added from the smallest level (L = S+1) to the
- *   largest (L = 2) in FP64, scaled by 2^(e_i + f_j), and the epilogue
+ * Step 4 (recombine): level L = s + t has unit 2^-(2 b1 + b (L-2)).  The kept
+ *   levels are summed exactly (an integer in units of the smallest level) and
+ *   rounded once to FP64, scaled by 2^(e_i + f_j), and the epilogue
  *   alpha*acc + beta*C is applied as in orc_gemm_f64.
  */
 
@@ -185,8 +188,12 @@ int orc_split_bits(int fmt, int *b1, int *b)
 {
     if (fmt == 0) { *b1 = 8; *b = 9; return 0; }
     if (fmt == 1) { *b1 = 4; *b = 5; return 0; }
+    if (fmt == 2) { *b1 = 7; *b = 7; return 0; }
     return -1;
 }
+
+/* 1: slices round to nearest (ties to even); 0: slices round toward zero. */
+static int split_nearest(int fmt) { return fmt != 2; }
 
 /* Exponent per row of an r x c row-major matrix (stride ld along rows). */
 void orc_split_row_exponents(int64_t r, int64_t c, const double *X, int64_t ld, int32_t *e)
@@ -218,15 +225,16 @@ void orc_split_col_exponents(int64_t r, int64_t c, const double *X, int64_t ld, 
     }
 }
 
-/* Slices of one value x0 = X * 2^-ex (|x0| < 1): writes S integers to q[0..S-1]
- * with stride qs; returns the final remainder (in units of the last piece). */
-static double slice_one(double v, int ex, int b1, int b, int S, int16_t *q, int64_t qs)
+/* Slices of one value v with exponent ex: writes S integers to q[0..S-1] with
+ * stride qs; returns the final remainder (in units of the last piece). */
+static double slice_one(double v, int ex, int b1, int b, int nearest, int S, int16_t *q,
+                        int64_t qs)
 {
     double x = ldexp(v, b1 - ex);
     double r = 0.0;
     for (int s = 0; s < S; ++s) {
         if (s > 0) x = ldexp(r, b);
-        double qi = nearbyint(x);
+        double qi = nearest ? nearbyint(x) : trunc(x);
         r = x - qi;
         q[(int64_t)s * qs] = (int16_t)qi;
     }
@@ -239,10 +247,11 @@ void orc_split_slices_rows(int64_t r, int64_t c, const double *X, int64_t ld,
 {
     int b1, b;
     orc_split_bits(fmt, &b1, &b);
+    const int nearest = split_nearest(fmt);
     const int64_t plane = r * c;
     for (int64_t i = 0; i < r; ++i)
         for (int64_t p = 0; p < c; ++p) {
-            double rr = slice_one(X[i * ld + p], e[i], b1, b, S, Q + i * c + p, plane);
+            double rr = slice_one(X[i * ld + p], e[i], b1, b, nearest, S, Q + i * c + p, plane);
             if (rem) rem[i * c + p] = rr;
         }
 }
@@ -253,10 +262,11 @@ void orc_split_slices_cols(int64_t r, int64_t c, const double *X, int64_t ld,
 {
     int b1, b;
     orc_split_bits(fmt, &b1, &b);
+    const int nearest = split_nearest(fmt);
     const int64_t plane = r * c;
     for (int64_t p = 0; p < r; ++p)
         for (int64_t j = 0; j < c; ++j) {
-            double rr = slice_one(X[p * ld + j], f[j], b1, b, S, Q + p * c + j, plane);
+            double rr = slice_one(X[p * ld + j], f[j], b1, b, nearest, S, Q + p * c + j, plane);
             if (rem) rem[p * c + j] = rr;
         }
 }
@@ -282,8 +292,10 @@ static int all_finite(int64_t r, int64_t c, const double *X, int64_t ld)
     return 1;
 }
 
-/* Full split-precision GEMM.  Returns 0, or ORC_ERR_NONFINITE (C untouched) when A
- * or B holds a NaN or an infinity.  S is the number of pieces per operand. */
+/* Full split-precision GEMM.  Returns 0, ORC_ERR_NONFINITE (C untouched) when A or
+ * B holds a NaN or an infinity, -13 for a bad format, -14 when the exact level
+ * sum would not fit the 128-bit accumulator (k too large).  S is the number of
+ * pieces per operand. */
 int orc_split_gemm(int64_t m, int64_t n, int64_t k, double alpha,
                    const double *A, int64_t lda, const double *B, int64_t ldb,
                    double beta, double *C, int64_t ldc, int fmt, int S, int nthreads)
@@ -296,7 +308,13 @@ int orc_split_gemm(int64_t m, int64_t n, int64_t k, double alpha,
     }
     if (!all_finite(m, k, A, lda) || !all_finite(k, n, B, ldb)) return ORC_ERR_NONFINITE;
     int b1, b;
-    if (orc_split_bits(fmt, &b1, &b) != 0 || S < 1) return -13;
+    if (orc_split_bits(fmt, &b1, &b) != 0 || S < 1 || S > 16) return -13;
+    /* largest level sum in units of the smallest kept level:
+     * (pairs) * D^2 * k * 2^(b (S-1)) must stay below 2^125 */
+    {
+        double bits = 2.0 * b1 + log2((double)k) + log2((double)S) + (double)b * (S - 1);
+        if (bits > 125.0) return -14;
+    }
 
     int32_t *e = (int32_t *)malloc(sizeof(int32_t) * (size_t)m);
     int32_t *f = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
@@ -315,11 +333,12 @@ int orc_split_gemm(int64_t m, int64_t n, int64_t k, double alpha,
             for (int64_t j = 0; j < n; ++j)
                 QBt[(int64_t)t * n * k + j * k + p] = QB[(int64_t)t * k * n + p * n + j];
 
+    const int lowest = 2 * b1 + b * (S - 1);   /* exponent of the unit of level S+1 */
 #pragma omp parallel for schedule(static) num_threads(nthreads)
     for (int64_t i = 0; i < m; ++i) {
         for (int64_t j = 0; j < n; ++j) {
-            double acc = 0.0;
-            for (int L = S + 1; L >= 2; --L) {
+            __int128 total = 0;
+            for (int L = 2; L <= S + 1; ++L) {
                 int64_t level = 0;
                 for (int s = 1; s <= S; ++s) {
                     int t = L - s;
@@ -330,9 +349,12 @@ int orc_split_gemm(int64_t m, int64_t n, int64_t k, double alpha,
                     for (int64_t p = 0; p < k; ++p) g += (int64_t)qa[p] * (int64_t)qb[p];
                     level += g;
                 }
-                acc = acc + ldexp((double)level, -(2 * b1 + b * (L - 2)));
+                /* level L in units of level S+1 */
+                total += (__int128)level * ((__int128)1 << (b * (S + 1 - L)));
             }
-            acc = ldexp(acc, e[i] + f[j]);
+            /* one rounding (IEEE conversion of the exact integer), then exact
+             * power-of-two scalings */
+            double acc = ldexp((double)total, -lowest + e[i] + f[j]);
             double *c = C + i * ldc + j;
             *c = (beta == 0.0) ? alpha * acc : alpha * acc + beta * *c;
         }

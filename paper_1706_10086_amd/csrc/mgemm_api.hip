@@ -112,19 +112,49 @@ static bool same_cfg(const mgemm_cfg &a, const mgemm_cfg &b) {
            a.occupancy == b.occupancy;
 }
 
-// Built-in choice when no configuration is given: the largest tile that still
-// gives every compute unit work, else the smallest tile.
-static const KernelEntry *default_entry(const KernelEntry *reg, int cnt, int64_t m, int64_t n) {
-    static const int kOrder[][3] = {{128, 128, 16}, {128, 64, 16}, {64, 64, 16}, {32, 32, 16}};
-    for (auto &o : kOrder) {
-        for (int i = 0; i < cnt; ++i) {
-            const mgemm_cfg &c = reg[i].cfg;
-            if (c.bm == o[0] && c.bn == o[1] && c.bk == o[2]) {
-                if (tiles_of(m, n, c) >= 256 || o[0] == 32) return &reg[i];
-            }
-        }
+// Built-in choice when no configuration is given: the first configuration of a
+// preference list (largest tiles first, from square-size sweeps on MI355X) that
+// still launches at least `min_tiles` work-groups; the last entry takes the rest.
+struct Pref {
+    mgemm_cfg cfg;
+    int64_t min_tiles;
+};
+
+static const Pref kPrefF64[] = {
+    {{256, 128, 16, 8, 2, 1, 0}, 512},
+    {{128, 128, 16, 4, 2, 1, 2}, 256},
+    {{128, 64, 32, 4, 4, 0, 2}, 256},
+    {{64, 64, 16, 4, 2, 1, 0}, 256},
+    {{32, 32, 16, 1, 2, 1, 0}, 0},
+};
+
+static const Pref kPrefF32[] = {
+    {{256, 128, 32, 8, 4, 1, 0}, 512},
+    {{128, 128, 32, 4, 4, 1, 0}, 256},
+    {{128, 64, 32, 4, 4, 1, 0}, 256},
+    {{64, 64, 16, 4, 2, 1, 0}, 256},
+    {{32, 32, 16, 1, 2, 1, 0}, 0},
+};
+
+static const KernelEntry *find_entry(const KernelEntry *reg, int cnt, const mgemm_cfg &c);
+
+static const KernelEntry *default_entry(int32_t dtype, const KernelEntry *reg, int cnt,
+                                        int64_t m, int64_t n) {
+    const Pref *pl = dtype == MGEMM_F32 ? kPrefF32 : kPrefF64;
+    const int np = dtype == MGEMM_F32 ? (int)(sizeof kPrefF32 / sizeof kPrefF32[0])
+                                      : (int)(sizeof kPrefF64 / sizeof kPrefF64[0]);
+    for (int i = 0; i < np; ++i) {
+        if (i + 1 < np && tiles_of(m, n, pl[i].cfg) < pl[i].min_tiles) continue;
+        const KernelEntry *e = find_entry(reg, cnt, pl[i].cfg);
+        if (e) return e;
     }
     return cnt > 0 ? &reg[0] : nullptr;
+}
+
+static const KernelEntry *find_entry(const KernelEntry *reg, int cnt, const mgemm_cfg &c) {
+    for (int i = 0; i < cnt; ++i)
+        if (same_cfg(reg[i].cfg, c)) return &reg[i];
+    return nullptr;
 }
 
 static bool aligned_rows(const void *p, int64_t ld, size_t es) {
@@ -159,14 +189,13 @@ int32_t gemm_ex(int64_t m, int64_t n, int64_t k, double alpha, const void *A, in
     const KernelEntry *reg = registry(dtype, &cnt);
     const KernelEntry *e = nullptr;
     if (cfg) {
-        for (int i = 0; i < cnt; ++i)
-            if (same_cfg(reg[i].cfg, *cfg)) { e = &reg[i]; break; }
+        e = find_entry(reg, cnt, *cfg);
         if (!e)
             return set_error(-13, "configuration %dx%dx%d w%d e%d d%d o%d is not registered",
                              cfg->bm, cfg->bn, cfg->bk, cfg->waves, cfg->elems_per_thread,
                              cfg->double_buffer, cfg->occupancy);
     } else {
-        e = default_entry(reg, cnt, m, n);
+        e = default_entry(dtype, reg, cnt, m, n);
         if (!e) return set_error(MGEMM_ERR_NOCONFIG, "no configuration for dtype %d", dtype);
     }
     const size_t es = elem_size(dtype);

@@ -22,6 +22,7 @@ U = 2.0 ** -53
 def test_slice_format_bits(orc):
     assert orc.split_bits(orc.FMT_BF16) == (8, 9)   # bfloat16: 8 significant bits
     assert orc.split_bits(orc.FMT_E4M3) == (4, 5)   # e4m3: 4 significant bits
+    assert orc.split_bits(orc.FMT_INT8) == (7, 7)   # int8: |q| <= 127, truncated
 
 
 @pytest.mark.parametrize("gen", ["uniform", "wide"])
@@ -46,17 +47,18 @@ def test_exponents_bracket_the_row_and_column_maxima(orc, gen):
             assert np.ldexp(1.0, int(fcol[j]) - 1) <= nu < np.ldexp(1.0, int(fcol[j]))
 
 
-@pytest.mark.parametrize("fmt,S", [(0, 6), (0, 3), (1, 11), (1, 5)])
+@pytest.mark.parametrize("fmt,S", [(0, 6), (0, 3), (1, 11), (1, 5), (2, 8), (2, 3)])
 def test_slices_reconstruct_exactly_and_respect_the_bound(orc, fmt, S):
     b1, b = orc.split_bits(fmt)
-    D = 2 ** b1
+    D = 2 ** b1 if fmt != 2 else 127
+    rmax = 0.5 if fmt != 2 else 1.0
     A = synth.wide_range((9, 13), 77)
     A[2, 5] = 0.0
     A[4, :] = 0.0
     e = orc.split_row_exponents(A)
     Q, rem = orc.split_slices_rows(A, e, fmt, S)
     assert np.all(np.abs(Q.astype(np.int64)) <= D)
-    assert np.all(np.abs(rem) <= 0.5)
+    assert np.all(np.abs(rem) <= rmax) and (fmt != 2 or np.all(np.abs(rem) < 1.0))
     for i in range(A.shape[0]):
         for p in range(A.shape[1]):
             acc = Fraction(0)
@@ -91,6 +93,21 @@ def test_slices_are_nearest_integers(orc):
     assert Q[1, 0, 2] == -256         # remainder -0.5
 
 
+def test_int8_slices_truncate_toward_zero(orc):
+    """b1 = b = 7 with truncation: 0.75 -> 96; 0.5 + 2^-8 -> 64.5 -> 64, remainder
+    0.5 -> 64; the negative mirror gives -64, -64 (not -65 / rounding away)."""
+    A = np.array([[0.75, 0.5 + 2.0 ** -8, -0.5 - 2.0 ** -8, 0.25 + 2.0 ** -20]])
+    e = orc.split_row_exponents(A)
+    assert e[0] == 0
+    Q, rem = orc.split_slices_rows(A, e, 2, 3)
+    assert list(Q[:, 0, 0]) == [96, 0, 0]
+    assert list(Q[:, 0, 1]) == [64, 64, 0]
+    assert list(Q[:, 0, 2]) == [-64, -64, 0]
+    # 0.25 + 2^-20: 32 + 2^-13 -> 32, then 2^-13 * 2^7 = 2^-6 -> 0, then 2^-6*2^7 = 2 -> 2
+    assert list(Q[:, 0, 3]) == [32, 0, 2]
+    assert np.all(rem[0] == 0.0)
+
+
 def test_pair_product_equals_numpy_int64(orc):
     QA = synth.integer_valued((23, 300), 1, 256).astype(np.int16)
     QB = synth.integer_valued((300, 19), 2, 256).astype(np.int16)
@@ -109,14 +126,15 @@ def split_bound(orc, A, B, fmt, S):
     e = orc.split_row_exponents(A).astype(np.float64)
     f = orc.split_col_exponents(B).astype(np.float64)
     scale = np.exp2(e[:, None] + f[None, :])
-    trunc = 2.0 * 0.5 * 2.0 ** -(b1 + b * (S - 1)) * (1 + 2.0 ** -(b1 + b * (S - 1)))
+    rmax = 0.5 if fmt != 2 else 1.0
+    trunc = 2.0 * rmax * 2.0 ** -(b1 + b * (S - 1)) * (1 + 2.0 ** -(b1 + b * (S - 1)))
     dropped = sum(2.0 ** -(b * (s + t - 2)) for s in range(1, S + 1) for t in range(1, S + 1)
                   if s + t > S + 1)
     absAB = np.abs(A) @ np.abs(B)
     return k * scale * (trunc + dropped) + (S + 2) * U * (absAB + k * scale * 2 ** -b1)
 
 
-@pytest.mark.parametrize("fmt,S", [(0, 6), (0, 4), (1, 11), (1, 7)])
+@pytest.mark.parametrize("fmt,S", [(0, 6), (0, 4), (1, 11), (1, 7), (2, 8), (2, 5)])
 def test_split_within_a_priori_bound_of_exact(orc, fmt, S):
     m, n, k = 5, 4, 9
     A = synth.wide_range((m, k), 91)
@@ -127,6 +145,33 @@ def test_split_within_a_priori_bound_of_exact(orc, fmt, S):
         for j in range(n):
             ex = sum((Fraction(A[i, p]) * Fraction(B[p, j]) for p in range(k)), Fraction(0))
             assert abs(Fraction(got[i, j]) - ex) <= Fraction(bound[i, j])
+
+
+@pytest.mark.parametrize("fmt,S", [(0, 6), (0, 3), (1, 11), (2, 8), (2, 4)])
+def test_split_is_the_kept_pairs_exact_sum_rounded_once(orc, fmt, S):
+    """Steps 3-4 pinned by exact rational arithmetic: with alpha = 1, beta = 0 the
+    result is the exact sum over kept pairs s + t <= S + 1 of the slice products,
+    scaled by 2^(e_i + f_j), correctly rounded (Python's float(Fraction) is)."""
+    b1, b = orc.split_bits(fmt)
+    m, n, k = 4, 3, 11
+    A = synth.wide_range((m, k), 71)
+    B = synth.wide_range((k, n), 72)
+    e = orc.split_row_exponents(A)
+    f = orc.split_col_exponents(B)
+    QA, _ = orc.split_slices_rows(A, e, fmt, S)
+    QB, _ = orc.split_slices_cols(B, f, fmt, S)
+    got = orc.split_gemm(1.0, A, B, fmt=fmt, S=S)
+    for i in range(m):
+        for j in range(n):
+            v = Fraction(0)
+            for s_ in range(S):
+                for t in range(S):
+                    if s_ + t + 2 > S + 1:
+                        continue
+                    g = sum(int(QA[s_, i, p]) * int(QB[t, p, j]) for p in range(k))
+                    v += Fraction(g) / Fraction(2) ** (2 * b1 + b * (s_ + t))
+            v *= Fraction(2) ** (int(e[i]) + int(f[j]))
+            assert got[i, j] == float(v)
 
 
 def test_split_bound_medium_vs_dot2_and_more_slices_help(orc):
