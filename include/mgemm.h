@@ -18,9 +18,11 @@
  *          (batched plans keep them until destroyed, see below).  C must not
  *          overlap A or B.
  * Types    MGEMM_F64: A, B, C are double.  MGEMM_F32: float (alpha, beta are
- *          rounded to float).  MGEMM_SPLIT_BF16 / MGEMM_SPLIT_FP8: A, B, C are
- *          double; the product is emulated from bfloat16 / FP8-e4m3 slices of A
- *          and B (Ozaki scheme), see gemm_ex.
+ *          rounded to float).  MGEMM_SPLIT_BF16 / MGEMM_SPLIT_INT8: A, B, C are
+ *          double; the product is emulated from bfloat16 (6 slices, 21 slice
+ *          pairs) / int8 (8 slices, 36 pairs) slices of A and B (Ozaki scheme),
+ *          see gemm_ex.  MGEMM_SPLIT_FP8 (e4m3 slices) is reserved and returns
+ *          MGEMM_ERR_NOCONFIG.
  * Stream   Work is enqueued on the given HIP stream (NULL: the stream set with
  *          mgemm_set_stream, by default the null stream) and the call returns
  *          after enqueueing.  Launch errors are reported at once; faults surface
@@ -54,7 +56,8 @@ typedef enum {
     MGEMM_F64 = 0,
     MGEMM_F32 = 1,
     MGEMM_SPLIT_BF16 = 2,
-    MGEMM_SPLIT_FP8 = 3
+    MGEMM_SPLIT_FP8 = 3,
+    MGEMM_SPLIT_INT8 = 4
 } mgemm_dtype;
 
 enum {
@@ -91,9 +94,19 @@ MGEMM_API int32_t gemm(int64_t m, int64_t n, int64_t k, double alpha,
 
 /* gemm with an explicit configuration (cfg == NULL: the library's choice; a cfg
  * that is not in the registry for dtype gives -13) and stream (argument 14,
- * a hipStream_t; NULL: the current library stream).  The split dtypes slice A and
- * B in a library-owned device workspace that grows on demand (MGEMM_ERR_NOMEM if
- * it cannot) and is kept until mgemm_release_workspace() or unload. */
+ * a hipStream_t; NULL: the current library stream).
+ *
+ * Split dtypes: A and B are scaled per row / column by powers of two, sliced
+ * into small integers and multiplied on matrix cores with exact accumulation;
+ * the kept slice-pair products (s + t <= S + 1) are summed exactly and rounded
+ * once to FP64, then C = alpha*v + beta*C.  For k above 131072 (bf16) or 16384
+ * (int8) the k-range is processed in passes, each rounded once.  The slices live
+ * in a library-owned device workspace (about 2*S*bytes*(m+n)*k) that grows on
+ * demand (MGEMM_ERR_NOMEM if it cannot) and is kept until
+ * mgemm_release_workspace() or unload.  The call waits once for the scaling
+ * step on the stream (to report MGEMM_ERR_NONFINITE before C is touched);
+ * split calls on one device are ordered through the shared workspace. cfg must
+ * be NULL. */
 MGEMM_API int32_t gemm_ex(int64_t m, int64_t n, int64_t k, double alpha,
                 const void *A, int64_t lda, const void *B, int64_t ldb,
                 double beta, void *C, int64_t ldc, int32_t dtype,
@@ -123,6 +136,16 @@ MGEMM_API int32_t mgemm_release_workspace(void);
  * a correct layout D = A*B.  Returns 0, -1 (dtype) or -2 (NULL buffer). */
 MGEMM_API int32_t mgemm_probe_mfma(int32_t dtype, const void *A, const void *B, void *D,
                                    void *stream);
+
+/* Diagnostic: one low-precision matrix-core step with operand and accumulator
+ * registers passed unchanged per lane, to pin the lane layouts the split path
+ * relies on.  kind 0: bf16 32x32x16 (float out), 1: int8 32x32x32 (int32 out),
+ * 2: bf16 16x16x32, 3: int8 16x16x64.  a, b: 64 x 16 bytes of device memory (the
+ * 16-byte operand of lane l at byte 16 l); d: 64 x 16 32-bit words (accumulator
+ * element r of lane l at word 16 l + r; 4 elements for kinds 2, 3).  Returns 0,
+ * -1 (kind) or -2 (NULL buffer). */
+MGEMM_API int32_t mgemm_probe_mfma_raw(int32_t kind, const void *a, const void *b, void *d,
+                                       void *stream);
 
 #ifdef __cplusplus
 }

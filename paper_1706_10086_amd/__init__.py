@@ -20,14 +20,16 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmgemm.so")
 
-F64, F32, SPLIT_BF16, SPLIT_FP8 = 0, 1, 2, 3
-DTYPE_NAMES = {F64: "f64", F32: "f32", SPLIT_BF16: "split_bf16", SPLIT_FP8: "split_fp8"}
+F64, F32, SPLIT_BF16, SPLIT_FP8, SPLIT_INT8 = 0, 1, 2, 3, 4
+DTYPE_NAMES = {F64: "f64", F32: "f32", SPLIT_BF16: "split_bf16", SPLIT_FP8: "split_fp8",
+               SPLIT_INT8: "split_int8"}
+SPLIT_SLICES = {SPLIT_BF16: 6, SPLIT_INT8: 8}
 ERR_HIP, ERR_NOMEM, ERR_NONFINITE, ERR_NOCONFIG, ERR_PLAN = 1, 2, 3, 4, 5
 
 # Every symbol include/mgemm.h declares.
 EXPORTED = [
     "gemm", "gemm_ex", "mgemm_set_stream", "mgemm_last_error", "mgemm_config_count",
-    "mgemm_config_get", "mgemm_release_workspace", "mgemm_probe_mfma",
+    "mgemm_config_get", "mgemm_release_workspace", "mgemm_probe_mfma", "mgemm_probe_mfma_raw",
 ]
 
 
@@ -86,6 +88,8 @@ def lib():
     L.mgemm_release_workspace.restype = i32
     L.mgemm_probe_mfma.argtypes = [i32, p, p, p, p]
     L.mgemm_probe_mfma.restype = i32
+    L.mgemm_probe_mfma_raw.argtypes = [i32, p, p, p, p]
+    L.mgemm_probe_mfma_raw.restype = i32
     _lib = L
     return L
 
@@ -189,3 +193,10 @@ def probe_mfma(dtype: int, A, B, D, stream=None) -> None:
     kernels assume; D receives the 16x16 product."""
     _check(lib().mgemm_probe_mfma(dtype, A.data_ptr(), B.data_ptr(), D.data_ptr(),
                                   _stream_handle(stream)))
+
+
+def probe_mfma_raw(kind: int, a, b, d, stream=None) -> None:
+    """Raw-register matrix-core step (see mgemm.h): a, b are 64x16-byte device
+    tensors, d a 64x16 32-bit device tensor."""
+    _check(lib().mgemm_probe_mfma_raw(kind, a.data_ptr(), b.data_ptr(), d.data_ptr(),
+                                      _stream_handle(stream)))

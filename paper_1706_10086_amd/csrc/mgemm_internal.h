@@ -35,6 +35,32 @@ struct KernelEntry {
 const KernelEntry *f64_registry(int *count);
 const KernelEntry *f32_registry(int *count);
 
+// ---------------------------------------------------------------------------
+// Work-group id -> C tile.
+// ---------------------------------------------------------------------------
+// The hardware hands consecutive work-group ids to the 8 XCDs in turn.  First
+// undo that dealing, so that logical ids [x*per, (x+1)*per) all run on XCD x;
+// then walk tiles in groups of GROUP_M tile-rows, column by column, so that a
+// run of consecutive logical ids covers a compact rectangle of C.
+__device__ inline void tile_of_block(int bid, int nblocks, int tiles_m, int tiles_n,
+                                     int &tm, int &tn) {
+    constexpr int XCDS = 8;
+    constexpr int GROUP_M = 8;
+    int full = (nblocks / XCDS) * XCDS;
+    int lid = bid;
+    if (bid < full) {
+        int per = full / XCDS;
+        lid = (bid % XCDS) * per + bid / XCDS;
+    }
+    int group_size = GROUP_M * tiles_n;
+    int group = lid / group_size;
+    int first_m = group * GROUP_M;
+    int gm = tiles_m - first_m < GROUP_M ? tiles_m - first_m : GROUP_M;
+    int in_group = lid - group * group_size;
+    tm = first_m + in_group % gm;
+    tn = in_group / gm;
+}
+
 // Number of work-groups a configuration launches for an m x n output.
 inline int64_t tiles_of(int64_t m, int64_t n, const mgemm_cfg &c) {
     return ((m + c.bm - 1) / c.bm) * ((n + c.bn - 1) / c.bn);

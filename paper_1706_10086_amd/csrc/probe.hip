@@ -47,3 +47,57 @@ extern "C" int32_t mgemm_probe_mfma(int32_t dtype, const void *A, const void *B,
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? 0 : set_error(MGEMM_ERR_HIP, "probe: %s", hipGetErrorString(e));
 }
+
+// ---------------------------------------------------------------------------
+// Raw-register probe of the low-precision matrix-core steps used by the split
+// path.  Lane l passes its operand registers unchanged and gets its accumulator
+// registers back, so a test can recover the lane layout of each instruction.
+//   kind 0: v_mfma_f32_32x32x16_bf16  a, b: 8 bf16 per lane;  d: 16 float per lane
+//   kind 1: v_mfma_i32_32x32x32_i8    a, b: 16 int8 per lane; d: 16 int32 per lane
+//   kind 2: v_mfma_f32_16x16x32_bf16  a, b: 8 bf16 per lane;  d: 4 float per lane
+//   kind 3: v_mfma_i32_16x16x64_i8    a, b: 16 int8 per lane; d: 4 int32 per lane
+// ---------------------------------------------------------------------------
+namespace mgemm {
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef float v16f __attribute__((ext_vector_type(16)));
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+__global__ void probe_raw_kernel(int kind, const uint4 *a, const uint4 *b, uint32_t *d) {
+    const int l = threadIdx.x;
+    const uint4 ua = a[l], ub = b[l];
+    if (kind == 0) {
+        v16f acc = {};
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(v8bf, ua),
+                                                      __builtin_bit_cast(v8bf, ub), acc, 0, 0, 0);
+        for (int r = 0; r < 16; ++r) d[l * 16 + r] = __float_as_uint(acc[r]);
+    } else if (kind == 1) {
+        v16i acc = {};
+        acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(__builtin_bit_cast(v4i, ua),
+                                                    __builtin_bit_cast(v4i, ub), acc, 0, 0, 0);
+        for (int r = 0; r < 16; ++r) d[l * 16 + r] = (uint32_t)acc[r];
+    } else if (kind == 2) {
+        v4f acc = {};
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, ua),
+                                                      __builtin_bit_cast(v8bf, ub), acc, 0, 0, 0);
+        for (int r = 0; r < 4; ++r) d[l * 16 + r] = __float_as_uint(acc[r]);
+    } else {
+        v4i acc = {};
+        acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(__builtin_bit_cast(v4i, ua),
+                                                    __builtin_bit_cast(v4i, ub), acc, 0, 0, 0);
+        for (int r = 0; r < 4; ++r) d[l * 16 + r] = (uint32_t)acc[r];
+    }
+}
+}  // namespace mgemm
+
+// a, b: 64 x 16 bytes (one 16-byte operand register group per lane); d: 64 x 16
+// 32-bit words (accumulator element r of lane l at d[16 l + r]).
+extern "C" int32_t mgemm_probe_mfma_raw(int32_t kind, const void *a, const void *b, void *d,
+                                        void *stream) {
+    if (kind < 0 || kind > 3) return mgemm::set_error(-1, "kind must be 0..3");
+    if (!a || !b || !d) return mgemm::set_error(-2, "NULL buffer");
+    hipLaunchKernelGGL(mgemm::probe_raw_kernel, dim3(1), dim3(64), 0, (hipStream_t)stream, kind,
+                       (const uint4 *)a, (const uint4 *)b, (uint32_t *)d);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? 0 : mgemm::set_error(MGEMM_ERR_HIP, "probe: %s", hipGetErrorString(e));
+}

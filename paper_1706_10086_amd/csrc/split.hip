@@ -1,0 +1,624 @@
+// Split-precision emulation of an FP64 GEMM on low-precision matrix cores
+// (Ozaki scheme: Ozaki, Ogita, Oishi, Rump, "Error-free transformations of
+// matrix multiplication by using fast routines of matrix multiplication and its
+// applications", Numer. Algorithms 59, 2012; on matrix engines: Mukunoki, Ozaki,
+// Ogita, Imamura, ISC 2020).
+//
+// C = alpha*A*B + beta*C with FP64 A, B, C:
+//  1. scale    e_i = exponent of max_p |A_ip| (2^(e_i-1) <= max < 2^e_i), f_j the
+//              same over column j of B; any NaN/Inf in A or B is reported.
+//  2. slice    x = A_ip 2^(b1-e_i); q_1 = round(x); x = (x - q_1) 2^b; q_2 = ...
+//              S integer slices per element, exactly representable in the slice
+//              format; B is sliced per column and stored transposed, so both
+//              operands are k-contiguous.
+//  3. products for every pair (s, t) with s + t <= S + 1 the integer product
+//              Q_A^(s) Q_B^(t) on matrix cores, summed per level L = s + t.  The
+//              sums are exact: bf16 products accumulate in FP32 in chunks small
+//              enough that every partial sum is an integer below 2^24 and are then
+//              added into two FP64 accumulators that hold exact integers (levels
+//              2-4 and 5-7); int8 products accumulate exactly in int32.
+//  4. combine  the exact sum of the kept levels is rounded once to FP64,
+//              scaled by 2^(e_i + f_j) and the epilogue alpha*v + beta*C applied.
+//
+// Formats: bf16 slices, b1 = 8, b = 9 bits, round to nearest, S = 6 (21 pairs);
+//          int8 slices, b1 = b = 7 bits, round toward zero, S = 8 (36 pairs).
+//
+// Workspace (device, owned by the library, grown on demand): exponents, a
+// non-finite flag and the slices, laid out per row as [row][k-chunk][slice][KC]
+// so that one k-chunk of all slices of a row is one contiguous run.
+#include <limits.h>
+
+#include <mutex>
+
+#include "mgemm_internal.h"
+
+namespace mgemm {
+
+int32_t set_error(int32_t code, const char *fmt, ...);
+
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef float v16f __attribute__((ext_vector_type(16)));
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+// 16 bytes as a native vector (HIP's uint4 is a union-based class that the
+// compiler cannot keep in registers when held in arrays)
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// Slice formats.
+// ---------------------------------------------------------------------------
+struct FmtBF16 {
+    static constexpr int S = 6;         // slices per operand
+    static constexpr int B1 = 8;        // bits of the first slice
+    static constexpr int B = 9;         // bits of each later slice
+    static constexpr bool NEAREST = true;
+    static constexpr int KC = 16;       // k per chunk = k of one MFMA step
+    static constexpr int ELEM = 2;      // bytes per slice element
+    // integer-valued q with |q| <= 256 -> bf16 bits (exact: <= 8 significant bits)
+    static __device__ inline uint32_t encode(double q) {
+        return __float_as_uint((float)q) >> 16;
+    }
+};
+
+struct FmtI8 {
+    static constexpr int S = 8;
+    static constexpr int B1 = 7;
+    static constexpr int B = 7;
+    static constexpr bool NEAREST = false;
+    static constexpr int KC = 32;
+    static constexpr int ELEM = 1;
+    static __device__ inline uint32_t encode(double q) { return (uint32_t)(uint8_t)(int8_t)(int)q; }
+};
+
+// bytes of one (row, k-chunk) run: all S slices of KC elements
+template <typename F> constexpr int run_bytes() { return F::S * F::KC * F::ELEM; }
+
+constexpr int KPAD = 64;     // k padded to a multiple of 64 (slice-B transpose tile)
+constexpr int PBM = 64;      // pair kernel tile rows
+constexpr int PBN = 128;     // pair kernel tile columns
+
+// ---------------------------------------------------------------------------
+// 1. Scale.
+// ---------------------------------------------------------------------------
+__global__ void split_init_kernel(int *fexp, int64_t np, int *flag) {
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < np;
+         j += (int64_t)gridDim.x * blockDim.x)
+        fexp[j] = INT_MIN;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *flag = 0;
+}
+
+__device__ inline int exponent_of(double mx) {
+    int ex = 0;
+    if (mx > 0.0) (void)frexp(mx, &ex);
+    return ex;
+}
+
+// One 256-thread block per row (grid-stride over rows).
+__global__ void __launch_bounds__(256)
+split_row_scale_kernel(const double *__restrict__ A, int64_t m, int64_t k, int64_t lda,
+                       int *__restrict__ e, int *flag) {
+    __shared__ double red[4];
+    __shared__ int bad_any[4];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int64_t i = blockIdx.x; i < m; i += gridDim.x) {
+        double mx = 0.0;
+        int bad = 0;
+        const double *row = A + i * lda;
+        for (int64_t p = tid; p < k; p += 256) {
+            double v = row[p];
+            if (!isfinite(v)) bad = 1;
+            else mx = fmax(mx, fabs(v));
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            mx = fmax(mx, __shfl_xor(mx, off));
+            bad |= __shfl_xor(bad, off);
+        }
+        if (lane == 0) { red[wave] = mx; bad_any[wave] = bad; }
+        __syncthreads();
+        if (tid == 0) {
+            double t = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+            if (bad_any[0] | bad_any[1] | bad_any[2] | bad_any[3]) *flag = 1;
+            e[i] = exponent_of(t);
+        }
+        __syncthreads();
+    }
+}
+
+// Thread per column, 64 rows per block row; exponents merged with atomicMax
+// (the exponent is non-decreasing in |x|).  Untouched (all-zero) columns keep
+// INT_MIN and are read as exponent 0.
+constexpr int COL_ROWS = 64;
+
+__global__ void __launch_bounds__(256)
+split_col_scale_kernel(const double *__restrict__ B, int64_t k, int64_t n, int64_t ldb,
+                       int *__restrict__ fexp, int *flag) {
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= n) return;
+    const int64_t nyb = (k + COL_ROWS - 1) / COL_ROWS;
+    for (int64_t yb = blockIdx.y; yb < nyb; yb += gridDim.y) {
+        const int64_t p0 = yb * COL_ROWS;
+        const int64_t p1 = p0 + COL_ROWS < k ? p0 + COL_ROWS : k;
+        double mx = 0.0;
+        int bad = 0;
+        for (int64_t p = p0; p < p1; ++p) {
+            double v = B[p * ldb + j];
+            if (!isfinite(v)) bad = 1;
+            else mx = fmax(mx, fabs(v));
+        }
+        if (bad) *flag = 1;
+        if (mx > 0.0) atomicMax(fexp + j, exponent_of(mx));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 2. Slice.
+// ---------------------------------------------------------------------------
+template <typename F>
+__device__ inline double slice_round(double x) {
+    return F::NEAREST ? rint(x) : trunc(x);
+}
+
+// 8 consecutive k values of one row of A -> S slices; rows >= m and k >= k are 0.
+template <typename F>
+__global__ void __launch_bounds__(256)
+split_slice_a_kernel(const double *__restrict__ A, int64_t m, int64_t k, int64_t lda,
+                     const int *__restrict__ e, uint8_t *__restrict__ QA, int64_t mp, int64_t kp) {
+    const int64_t groups_per_row = kp / 8;
+    const int64_t total = mp * groups_per_row;
+    const int64_t nch = kp / F::KC;
+    for (int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gid < total;
+         gid += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = gid / groups_per_row;
+        const int64_t p0 = (gid - i * groups_per_row) * 8;
+        const int ex = i < m ? e[i] : 0;
+        double x[8];
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+            const int64_t p = p0 + v;
+            x[v] = (i < m && p < k) ? ldexp(A[i * lda + p], F::B1 - ex) : 0.0;
+        }
+        uint8_t *dst = QA + ((i * nch + p0 / F::KC) * F::S) * F::KC * F::ELEM +
+                       (p0 % F::KC) * F::ELEM;
+#pragma unroll
+        for (int s = 0; s < F::S; ++s) {
+            uint32_t w[4] = {0, 0, 0, 0};
+#pragma unroll
+            for (int v = 0; v < 8; ++v) {
+                const double q = slice_round<F>(x[v]);
+                x[v] = (x[v] - q) * (double)(1 << F::B);
+                const uint32_t c = F::encode(q);
+                if (F::ELEM == 2) w[v >> 1] |= c << (16 * (v & 1));
+                else w[v >> 2] |= c << (8 * (v & 3));
+            }
+            uint8_t *d = dst + (int64_t)s * F::KC * F::ELEM;
+            if (F::ELEM == 2) *(uint4 *)d = make_uint4(w[0], w[1], w[2], w[3]);
+            else *(uint2 *)d = make_uint2(w[0], w[1]);
+        }
+    }
+}
+
+// 64 (k) x 64 (n) tile of B through LDS; thread (j, 16 consecutive k) -> S slices
+// of column j stored k-contiguous.
+template <typename F>
+__global__ void __launch_bounds__(256)
+split_slice_b_kernel(const double *__restrict__ B, int64_t k, int64_t n, int64_t ldb,
+                     const int *__restrict__ fexp, uint8_t *__restrict__ QB, int64_t kp) {
+    __shared__ double tile[64][65];
+    const int tid = threadIdx.x;
+    const int64_t j0 = (int64_t)blockIdx.x * 64;
+    const int64_t p0 = (int64_t)blockIdx.y * 64;
+    for (int idx = tid; idx < 64 * 64; idx += 256) {
+        const int pr = idx >> 6, jc = idx & 63;
+        const int64_t p = p0 + pr, j = j0 + jc;
+        tile[pr][jc] = (p < k && j < n) ? B[p * ldb + j] : 0.0;
+    }
+    __syncthreads();
+    const int jc = tid >> 2;
+    const int pg = (tid & 3) * 16;
+    const int64_t j = j0 + jc;
+    const int fe = j < n ? fexp[j] : INT_MIN;
+    const int ex = fe == INT_MIN ? 0 : fe;
+    double x[16];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) x[v] = ldexp(tile[pg + v][jc], F::B1 - ex);
+    const int64_t nch = kp / F::KC;
+    const int64_t pabs = p0 + pg;
+    uint8_t *dst = QB + ((j * nch + pabs / F::KC) * F::S) * F::KC * F::ELEM +
+                   (pabs % F::KC) * F::ELEM;
+#pragma unroll
+    for (int s = 0; s < F::S; ++s) {
+        uint32_t w[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const double q = slice_round<F>(x[v]);
+            x[v] = (x[v] - q) * (double)(1 << F::B);
+            const uint32_t c = F::encode(q);
+            if (F::ELEM == 2) w[v >> 1] |= c << (16 * (v & 1));
+            else w[v >> 2] |= c << (8 * (v & 3));
+        }
+        uint8_t *d = dst + (int64_t)s * F::KC * F::ELEM;
+        if (F::ELEM == 2) {
+            ((uint4 *)d)[0] = make_uint4(w[0], w[1], w[2], w[3]);
+            ((uint4 *)d)[1] = make_uint4(w[4], w[5], w[6], w[7]);
+        } else {
+            *(uint4 *)d = make_uint4(w[0], w[1], w[2], w[3]);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 3-4. Slice-pair products and recombination.
+// ---------------------------------------------------------------------------
+// Work-group: 8 waves (2 x 4) own a 64 x 128 tile of C; each wave one 32 x 32
+// block (one 32x32 MFMA accumulator per level).  Per k-chunk the S slices of the
+// 64 A rows and 128 B columns are staged in LDS (double buffered); the 16-byte
+// units of one row are padded to an odd count so the fragment reads of 16
+// consecutive rows hit distinct banks.
+struct PairArgs {
+    const uint8_t *QA;
+    const uint8_t *QB;
+    const int *e;
+    const int *fexp;
+    double *C;
+    int64_t m, n, ldc;
+    int64_t nch;        // k-chunks per row in the slice layout
+    int64_t ch0, ch1;   // chunk range of this pass
+    double alpha, beta;
+    int tiles_m, tiles_n;
+};
+
+// 32x32 MFMA accumulator element r of lane l -> (row, column) in the wave block
+__device__ inline int acc_row(int lane, int r) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }
+
+// Stores the combined value of one element: v = fma(hi, 2^-lo_hi_shift ...)
+__device__ inline void store_c(const PairArgs &a, int64_t row, int64_t col, double v) {
+    if (row >= a.m || col >= a.n) return;
+    const int fe = a.fexp[col];
+    const int ex = a.e[row] + (fe == INT_MIN ? 0 : fe);
+    const double val = ldexp(v, ex);
+    double *c = a.C + row * a.ldc + col;
+    if (a.beta == 0.0) {
+        *c = a.alpha * val;
+    } else {
+#pragma clang fp contract(off)
+        *c = a.alpha * val + a.beta * *c;
+    }
+}
+
+template <typename F>
+struct PairTile {
+    static constexpr int UNITS = run_bytes<F>() / 16;   // 16-byte units per row run
+    static constexpr int SROW = UNITS + 1;               // padded LDS row (odd)
+    static constexpr int NT = 512;
+    static constexpr int TOTAL_UNITS = (PBM + PBN) * UNITS;
+    static constexpr int LOADS = (TOTAL_UNITS + NT - 1) / NT;
+};
+
+template <typename F>
+__device__ __attribute__((always_inline)) inline void pair_load(const PairArgs &a, int64_t m0, int64_t n0, int64_t ch,
+                                 u32x4 (&stage)[PairTile<F>::LOADS]) {
+    typedef PairTile<F> P;
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int it = 0; it < P::LOADS; ++it) {
+        const int u = tid + it * P::NT;
+        if (u < P::TOTAL_UNITS) {
+            const u32x4 *src;
+            if (u < PBM * P::UNITS) {
+                const int row = u / P::UNITS, c = u % P::UNITS;
+                src = (const u32x4 *)(a.QA + ((m0 + row) * a.nch + ch) * run_bytes<F>()) + c;
+            } else {
+                const int v = u - PBM * P::UNITS;
+                const int row = v / P::UNITS, c = v % P::UNITS;
+                src = (const u32x4 *)(a.QB + ((n0 + row) * a.nch + ch) * run_bytes<F>()) + c;
+            }
+            stage[it] = *src;
+        }
+    }
+}
+
+template <typename F>
+__device__ __attribute__((always_inline)) inline void pair_store(u32x4 *sA, u32x4 *sB, const u32x4 (&stage)[PairTile<F>::LOADS]) {
+    typedef PairTile<F> P;
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int it = 0; it < P::LOADS; ++it) {
+        const int u = tid + it * P::NT;
+        if (u < P::TOTAL_UNITS) {
+            if (u < PBM * P::UNITS) {
+                const int row = u / P::UNITS, c = u % P::UNITS;
+                sA[row * P::SROW + c] = stage[it];
+            } else {
+                const int v = u - PBM * P::UNITS;
+                const int row = v / P::UNITS, c = v % P::UNITS;
+                sB[row * P::SROW + c] = stage[it];
+            }
+        }
+    }
+}
+
+// bf16: six FP32 level accumulators, flushed exactly into FP64 (hi: levels 2-4 in
+// units of level 4; lo: levels 5-7 in units of level 7).  Flush periods (in
+// 16-deep chunks) keep every FP32 partial sum an integer of magnitude <= 2^24:
+// level L has (L-1) pairs of products <= 2^16, so it may run 256/(L-1) k-steps.
+__global__ void __launch_bounds__(512)
+split_pairs_bf16_kernel(PairArgs a) {
+    typedef FmtBF16 F;
+    typedef PairTile<F> P;
+    __shared__ u32x4 sA[2][PBM * P::SROW];
+    __shared__ u32x4 sB[2][PBN * P::SROW];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 2, wn = wave & 3;
+    int tm, tn;
+    tile_of_block(blockIdx.x, gridDim.x, a.tiles_m, a.tiles_n, tm, tn);
+    const int64_t m0 = (int64_t)tm * PBM, n0 = (int64_t)tn * PBN;
+
+    v16f acc[6];
+#pragma unroll
+    for (int l = 0; l < 6; ++l) acc[l] = v16f{};
+    double hi[16], lo[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) { hi[r] = 0.0; lo[r] = 0.0; }
+
+    const int r32 = lane & 31, kh = lane >> 5;
+    const int a_off = (wm * 32 + r32) * P::SROW + kh;
+    const int b_off = (wn * 32 + r32) * P::SROW + kh;
+
+    u32x4 stage[P::LOADS];
+    pair_load<F>(a, m0, n0, a.ch0, stage);
+    pair_store<F>(sA[0], sB[0], stage);
+    __syncthreads();
+
+    constexpr int PERIOD[6] = {16, 8, 4, 4, 2, 2};
+    for (int64_t ch = a.ch0; ch < a.ch1; ++ch) {
+        const int cur = (int)((ch - a.ch0) & 1);
+        const bool more = ch + 1 < a.ch1;
+        if (more) pair_load<F>(a, m0, n0, ch + 1, stage);
+
+        v8bf fa[6], fb[6];
+#pragma unroll
+        for (int s = 0; s < 6; ++s) {
+            fa[s] = __builtin_bit_cast(v8bf, sA[cur][a_off + 2 * s]);
+            fb[s] = __builtin_bit_cast(v8bf, sB[cur][b_off + 2 * s]);
+        }
+#pragma unroll
+        for (int lv = 0; lv < 6; ++lv)
+#pragma unroll
+            for (int s = 0; s <= lv; ++s)
+                acc[lv] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[s], fb[lv - s], acc[lv], 0, 0, 0);
+
+        const int64_t done = ch - a.ch0 + 1;
+#pragma unroll
+        for (int lv = 0; lv < 6; ++lv) {
+            if (done % PERIOD[lv] == 0 || !more) {
+                // hi holds levels 2..4 (lv 0..2) in units of level 4, lo levels
+                // 5..7 (lv 3..5) in units of level 7: both stay exact integers
+                const double sc = (double)(1 << (9 * (2 - (lv % 3))));
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    if (lv < 3) hi[r] = fma((double)acc[lv][r], sc, hi[r]);
+                    else lo[r] = fma((double)acc[lv][r], sc, lo[r]);
+                }
+                acc[lv] = v16f{};
+            }
+        }
+        if (more) pair_store<F>(sA[cur ^ 1], sB[cur ^ 1], stage);
+        __syncthreads();
+    }
+
+    // exact value = hi 2^-34 + lo 2^-61, rounded once
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const double v = fma(hi[r], 0x1p-34, lo[r] * 0x1p-61);
+        store_c(a, m0 + wm * 32 + acc_row(lane, r), n0 + wn * 32 + r32, v);
+    }
+}
+
+// int8: eight int32 level accumulators (exact for k <= 16384 per pass), combined
+// exactly at the end into hi (levels 2-5, units of level 5) and lo (levels 6-9,
+// units of level 9).
+__global__ void __launch_bounds__(512)
+split_pairs_i8_kernel(PairArgs a) {
+    typedef FmtI8 F;
+    typedef PairTile<F> P;
+    __shared__ u32x4 sA[2][PBM * P::SROW];
+    __shared__ u32x4 sB[2][PBN * P::SROW];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 2, wn = wave & 3;
+    int tm, tn;
+    tile_of_block(blockIdx.x, gridDim.x, a.tiles_m, a.tiles_n, tm, tn);
+    const int64_t m0 = (int64_t)tm * PBM, n0 = (int64_t)tn * PBN;
+
+    v16i acc[8];
+#pragma unroll
+    for (int l = 0; l < 8; ++l) acc[l] = v16i{};
+
+    const int r32 = lane & 31, kh = lane >> 5;
+    const int a_off = (wm * 32 + r32) * P::SROW + kh;
+    const int b_off = (wn * 32 + r32) * P::SROW + kh;
+
+    u32x4 stage[P::LOADS];
+    pair_load<F>(a, m0, n0, a.ch0, stage);
+    pair_store<F>(sA[0], sB[0], stage);
+    __syncthreads();
+
+    for (int64_t ch = a.ch0; ch < a.ch1; ++ch) {
+        const int cur = (int)((ch - a.ch0) & 1);
+        const bool more = ch + 1 < a.ch1;
+        if (more) pair_load<F>(a, m0, n0, ch + 1, stage);
+
+        v4i fa[8], fb[8];
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            fa[s] = __builtin_bit_cast(v4i, sA[cur][a_off + 2 * s]);
+            fb[s] = __builtin_bit_cast(v4i, sB[cur][b_off + 2 * s]);
+        }
+#pragma unroll
+        for (int lv = 0; lv < 8; ++lv)
+#pragma unroll
+            for (int s = 0; s <= lv; ++s)
+                acc[lv] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[s], fb[lv - s], acc[lv], 0, 0, 0);
+
+        if (more) pair_store<F>(sA[cur ^ 1], sB[cur ^ 1], stage);
+        __syncthreads();
+    }
+
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        double hi = (double)acc[0][r] * 0x1p21;
+        hi = hi + (double)acc[1][r] * 0x1p14;
+        hi = hi + (double)acc[2][r] * 0x1p7;
+        hi = hi + (double)acc[3][r];
+        double lo = (double)acc[4][r] * 0x1p21;
+        lo = lo + (double)acc[5][r] * 0x1p14;
+        lo = lo + (double)acc[6][r] * 0x1p7;
+        lo = lo + (double)acc[7][r];
+        const double v = fma(hi, 0x1p-35, lo * 0x1p-63);
+        store_c(a, m0 + wm * 32 + acc_row(lane, r), n0 + wn * 32 + r32, v);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host side: workspace and driver.
+// ---------------------------------------------------------------------------
+constexpr int MAX_DEVICES = 64;
+
+struct Workspace {
+    std::mutex mtx;
+    uint8_t *base = nullptr;
+    size_t bytes = 0;
+    int *host_flag = nullptr;        // pinned
+    hipEvent_t done = nullptr;       // last split work that used the workspace
+};
+
+static Workspace g_ws[MAX_DEVICES];
+
+static int32_t ws_reserve(Workspace &w, size_t bytes) {
+    if (!w.done) {
+        if (hipEventCreateWithFlags(&w.done, hipEventDisableTiming) != hipSuccess)
+            return set_error(MGEMM_ERR_HIP, "split: event create failed");
+    }
+    if (!w.host_flag) {
+        if (hipHostMalloc((void **)&w.host_flag, sizeof(int), hipHostMallocDefault) != hipSuccess)
+            return set_error(MGEMM_ERR_NOMEM, "split: pinned flag allocation failed");
+    }
+    if (w.bytes >= bytes) return 0;
+    if (w.base) {
+        hipEventSynchronize(w.done);
+        hipFree(w.base);
+        w.base = nullptr;
+        w.bytes = 0;
+    }
+    if (hipMalloc((void **)&w.base, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        w.base = nullptr;
+        return set_error(MGEMM_ERR_NOMEM, "split: workspace of %zu bytes not available", bytes);
+    }
+    w.bytes = bytes;
+    return 0;
+}
+
+static inline int64_t round_up(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
+
+template <typename F>
+static int32_t run_split(const GemmArgs &g, hipStream_t s, Workspace &w, int max_pass_k,
+                         void (*pairs)(PairArgs)) {
+    const int64_t mp = round_up(g.m, PBM), np = round_up(g.n, PBN), kp = round_up(g.k, KPAD);
+    const size_t a_bytes = (size_t)mp * kp * F::S * F::ELEM;
+    const size_t b_bytes = (size_t)np * kp * F::S * F::ELEM;
+    const size_t e_bytes = round_up(mp * 4, 256), f_bytes = round_up(np * 4, 256);
+    const size_t total = e_bytes + f_bytes + 256 + a_bytes + b_bytes;
+    int32_t rc = ws_reserve(w, total);
+    if (rc) return rc;
+    int *e = (int *)w.base;
+    int *fexp = (int *)(w.base + e_bytes);
+    int *flag = (int *)(w.base + e_bytes + f_bytes);
+    uint8_t *QA = w.base + e_bytes + f_bytes + 256;
+    uint8_t *QB = QA + a_bytes;
+
+    hipError_t he = hipStreamWaitEvent(s, w.done, 0);
+    if (he != hipSuccess) return set_error(MGEMM_ERR_HIP, "split: %s", hipGetErrorString(he));
+    hipLaunchKernelGGL(split_init_kernel, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s,
+                       fexp, np, flag);
+    hipLaunchKernelGGL(split_row_scale_kernel, dim3((unsigned)(g.m < 65536 ? g.m : 65536)),
+                       dim3(256), 0, s, (const double *)g.A, g.m, g.k, g.lda, e, flag);
+    {
+        int64_t gy = (g.k + COL_ROWS - 1) / COL_ROWS;
+        if (gy > 65535) gy = 65535;
+        hipLaunchKernelGGL(split_col_scale_kernel, dim3((unsigned)((g.n + 255) / 256), (unsigned)gy),
+                           dim3(256), 0, s, (const double *)g.B, g.k, g.n, g.ldb, fexp, flag);
+    }
+    he = hipMemcpyAsync(w.host_flag, flag, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (he == hipSuccess) he = hipStreamSynchronize(s);
+    if (he != hipSuccess) return set_error(MGEMM_ERR_HIP, "split scale: %s", hipGetErrorString(he));
+    if (*w.host_flag) return set_error(MGEMM_ERR_NONFINITE, "split: A or B holds NaN or Inf");
+
+    {
+        int64_t groups = mp * (kp / 8);
+        int64_t blocks = (groups + 255) / 256;
+        if (blocks > 1 << 20) blocks = 1 << 20;
+        hipLaunchKernelGGL(split_slice_a_kernel<F>, dim3((unsigned)blocks), dim3(256), 0, s,
+                           (const double *)g.A, g.m, g.k, g.lda, (const int *)e, QA, mp, kp);
+        hipLaunchKernelGGL(split_slice_b_kernel<F>, dim3((unsigned)(np / 64), (unsigned)(kp / 64)),
+                           dim3(256), 0, s, (const double *)g.B, g.k, g.n, g.ldb,
+                           (const int *)fexp, QB, kp);
+    }
+
+    PairArgs pa;
+    pa.QA = QA;
+    pa.QB = QB;
+    pa.e = e;
+    pa.fexp = fexp;
+    pa.C = (double *)g.C;
+    pa.m = g.m;
+    pa.n = g.n;
+    pa.ldc = g.ldc;
+    pa.nch = kp / F::KC;
+    pa.alpha = g.alpha;
+    pa.tiles_m = (int)(mp / PBM);
+    pa.tiles_n = (int)(np / PBN);
+    const int64_t blocks = (int64_t)pa.tiles_m * pa.tiles_n;
+    const int64_t pass_ch = max_pass_k / F::KC;
+    const int64_t kch = (g.k + F::KC - 1) / F::KC;   // chunks holding data
+    for (int64_t c0 = 0; c0 < kch; c0 += pass_ch) {
+        pa.ch0 = c0;
+        pa.ch1 = c0 + pass_ch < kch ? c0 + pass_ch : kch;
+        pa.beta = c0 == 0 ? g.beta : 1.0;
+        hipLaunchKernelGGL(pairs, dim3((unsigned)blocks), dim3(512), 0, s, pa);
+    }
+    he = hipGetLastError();
+    if (he != hipSuccess) return set_error(MGEMM_ERR_HIP, "split launch: %s", hipGetErrorString(he));
+    hipEventRecord(w.done, s);
+    return 0;
+}
+
+int32_t split_gemm(const GemmArgs &g, int32_t dtype, hipStream_t s) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES)
+        return set_error(MGEMM_ERR_HIP, "split: no current device");
+    Workspace &w = g_ws[dev];
+    std::lock_guard<std::mutex> lock(w.mtx);
+    if (dtype == MGEMM_SPLIT_BF16) return run_split<FmtBF16>(g, s, w, 1 << 17, split_pairs_bf16_kernel);
+    if (dtype == MGEMM_SPLIT_INT8) return run_split<FmtI8>(g, s, w, 1 << 14, split_pairs_i8_kernel);
+    return set_error(MGEMM_ERR_NOCONFIG, "split dtype %d is not built", dtype);
+}
+
+int32_t split_release() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return 0;
+    Workspace &w = g_ws[dev];
+    std::lock_guard<std::mutex> lock(w.mtx);
+    if (w.base) {
+        hipEventSynchronize(w.done);
+        hipFree(w.base);
+        w.base = nullptr;
+        w.bytes = 0;
+    }
+    return 0;
+}
+
+}  // namespace mgemm
+
+extern "C" int32_t mgemm_release_workspace(void) { return mgemm::split_release(); }
