@@ -112,6 +112,51 @@ MGEMM_API int32_t gemm_ex(int64_t m, int64_t n, int64_t k, double alpha,
                 double beta, void *C, int64_t ldc, int32_t dtype,
                 const mgemm_cfg *cfg, void *stream);
 
+/*
+ * Batched GEMM: count independent problems C_i = alpha_i A_i B_i + beta_i C_i
+ * (Eq. 1 per problem), dtype MGEMM_F64 or MGEMM_F32 for plans (any dtype for
+ * gemm_batched).  All array arguments are HOST arrays of count entries; A, B, C
+ * hold DEVICE pointers.  Problem arguments are checked as in gemm (an invalid
+ * problem returns that argument's -i code and names the problem in
+ * mgemm_last_error).
+ *
+ * gemm_batched: one gemm launch per problem, in order, on the current stream.
+ * Array arguments are numbered 2..12 after count (1); dtype is 13.
+ */
+MGEMM_API int32_t gemm_batched(int64_t count, const int64_t *m, const int64_t *n,
+                               const int64_t *k, const double *alpha, const void *const *A,
+                               const int64_t *lda, const void *const *B, const int64_t *ldb,
+                               const double *beta, void *const *C, const int64_t *ldc,
+                               int32_t dtype);
+
+/* Builds a reusable plan for one batched launch: problems are grouped by tile
+ * configuration (cfgs[i], or the library's choice when cfgs is NULL) and row
+ * alignment; per group one persistent kernel takes C tiles from an atomic work
+ * list; all groups are captured into one HIP graph.  The plan keeps the problem
+ * descriptors (pointers, sizes, alpha, beta) -- the matrices must stay valid and
+ * are read at each execution.  Problems with k == 0 or alpha == 0 are rejected
+ * (MGEMM_ERR_PLAN).  stream: the stream executions run on (NULL: null stream).
+ * Results are bitwise identical to gemm_ex with the same configurations.
+ * *plan receives an opaque handle; returns 0 or an error code. */
+MGEMM_API int32_t gemm_batched_plan_create(int64_t count, const int64_t *m, const int64_t *n,
+                                           const int64_t *k, const double *alpha,
+                                           const void *const *A, const int64_t *lda,
+                                           const void *const *B, const int64_t *ldb,
+                                           const double *beta, void *const *C,
+                                           const int64_t *ldc, int32_t dtype,
+                                           const mgemm_cfg *cfgs, void *stream, void **plan);
+
+/* Runs a plan: one hipGraphLaunch on the plan's stream (asynchronous).
+ * Executions of one plan must not overlap (they share the work counters). */
+MGEMM_API int32_t gemm_batched_plan_execute(void *plan);
+
+/* Waits for the plan's stream and frees the plan (NULL is a no-op). */
+MGEMM_API int32_t gemm_batched_plan_destroy(void *plan);
+
+/* Number of configuration groups, total C tiles and total 2*m*n*k of a plan. */
+MGEMM_API int32_t gemm_batched_plan_info(void *plan, int32_t *buckets, int64_t *total_tiles,
+                                         double *flops);
+
 /* Sets the stream used when a call passes NULL; returns 0. */
 MGEMM_API int32_t mgemm_set_stream(void *stream);
 

@@ -30,6 +30,8 @@ ERR_HIP, ERR_NOMEM, ERR_NONFINITE, ERR_NOCONFIG, ERR_PLAN = 1, 2, 3, 4, 5
 EXPORTED = [
     "gemm", "gemm_ex", "mgemm_set_stream", "mgemm_last_error", "mgemm_config_count",
     "mgemm_config_get", "mgemm_release_workspace", "mgemm_probe_mfma", "mgemm_probe_mfma_raw",
+    "gemm_batched", "gemm_batched_plan_create", "gemm_batched_plan_execute",
+    "gemm_batched_plan_destroy", "gemm_batched_plan_info",
 ]
 
 
@@ -90,6 +92,17 @@ def lib():
     L.mgemm_probe_mfma.restype = i32
     L.mgemm_probe_mfma_raw.argtypes = [i32, p, p, p, p]
     L.mgemm_probe_mfma_raw.restype = i32
+    arr = [i64, p, p, p, p, p, p, p, p, p, p, p, i32]
+    L.gemm_batched.argtypes = arr
+    L.gemm_batched.restype = i32
+    L.gemm_batched_plan_create.argtypes = arr + [p, p, ctypes.POINTER(p)]
+    L.gemm_batched_plan_create.restype = i32
+    L.gemm_batched_plan_execute.argtypes = [p]
+    L.gemm_batched_plan_execute.restype = i32
+    L.gemm_batched_plan_destroy.argtypes = [p]
+    L.gemm_batched_plan_destroy.restype = i32
+    L.gemm_batched_plan_info.argtypes = [p, p, p, p]
+    L.gemm_batched_plan_info.restype = i32
     _lib = L
     return L
 
@@ -200,3 +213,80 @@ def probe_mfma_raw(kind: int, a, b, d, stream=None) -> None:
     tensors, d a 64x16 32-bit device tensor."""
     _check(lib().mgemm_probe_mfma_raw(kind, a.data_ptr(), b.data_ptr(), d.data_ptr(),
                                       _stream_handle(stream)))
+
+
+class _BatchArrays:
+    """Host arrays (kept alive) describing a list of problems."""
+
+    def __init__(self, As, Bs, Cs, alphas, betas):
+        import numpy as np
+        cnt = len(As)
+        self.count = cnt
+        self.m = np.array([a.shape[0] for a in As], dtype=np.int64)
+        self.k = np.array([a.shape[1] for a in As], dtype=np.int64)
+        self.n = np.array([b.shape[1] for b in Bs], dtype=np.int64)
+        self.lda = np.array([_ld(a) for a in As], dtype=np.int64)
+        self.ldb = np.array([_ld(b) for b in Bs], dtype=np.int64)
+        self.ldc = np.array([_ld(c) for c in Cs], dtype=np.int64)
+        self.alpha = np.ascontiguousarray(np.broadcast_to(np.asarray(alphas, dtype=np.float64), (cnt,)))
+        self.beta = np.ascontiguousarray(np.broadcast_to(np.asarray(betas, dtype=np.float64), (cnt,)))
+        self.A = (ctypes.c_void_p * cnt)(*[a.data_ptr() for a in As])
+        self.B = (ctypes.c_void_p * cnt)(*[b.data_ptr() for b in Bs])
+        self.C = (ctypes.c_void_p * cnt)(*[c.data_ptr() for c in Cs])
+        for a, b, c in zip(As, Bs, Cs):
+            if a.shape[1] != b.shape[0] or tuple(c.shape) != (a.shape[0], b.shape[1]):
+                raise ValueError("shape mismatch in batch")
+
+    def args(self):
+        P = lambda x: x.ctypes.data if hasattr(x, "ctypes") else ctypes.cast(x, ctypes.c_void_p).value
+        return (self.count, P(self.m), P(self.n), P(self.k), P(self.alpha), P(self.A), P(self.lda),
+                P(self.B), P(self.ldb), P(self.beta), P(self.C), P(self.ldc))
+
+
+def gemm_batched(As, Bs, Cs, alphas=1.0, betas=0.0, dtype=None) -> None:
+    """C_i <- alpha_i A_i B_i + beta_i C_i, one library launch per problem."""
+    if not As:
+        return
+    arrs = _BatchArrays(As, Bs, Cs, alphas, betas)
+    dtype = dtype_of(As[0]) if dtype is None else dtype
+    _check(lib().gemm_batched(*arrs.args(), dtype))
+
+
+class BatchedPlan:
+    """A captured batched launch (see gemm_batched_plan_create in mgemm.h).
+    ``cfgs``: None (library choice) or one Cfg / tuple per problem."""
+
+    def __init__(self, As, Bs, Cs, alphas=1.0, betas=0.0, dtype=None, cfgs=None, stream=None):
+        self._arrs = _BatchArrays(As, Bs, Cs, alphas, betas)
+        self.dtype = dtype_of(As[0]) if dtype is None and As else (dtype or F64)
+        cfg_arr = None
+        if cfgs is not None:
+            cfg_arr = (Cfg * len(cfgs))(*[c if isinstance(c, Cfg) else Cfg(*c) for c in cfgs])
+        self._cfgs = cfg_arr
+        self.handle = ctypes.c_void_p()
+        _check(lib().gemm_batched_plan_create(
+            *self._arrs.args(), self.dtype,
+            ctypes.cast(cfg_arr, ctypes.c_void_p).value if cfg_arr is not None else None,
+            _stream_handle(stream), ctypes.byref(self.handle)))
+
+    def execute(self) -> None:
+        _check(lib().gemm_batched_plan_execute(self.handle))
+
+    def info(self):
+        b = ctypes.c_int32()
+        t = ctypes.c_int64()
+        f = ctypes.c_double()
+        _check(lib().gemm_batched_plan_info(self.handle, ctypes.byref(b), ctypes.byref(t),
+                                            ctypes.byref(f)))
+        return {"buckets": b.value, "tiles": t.value, "flops": f.value}
+
+    def destroy(self) -> None:
+        if self.handle:
+            lib().gemm_batched_plan_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

@@ -75,15 +75,25 @@ __device__ inline T scale_add(T alpha, T acc, T beta, T c) {
 // WGM,WGN waves along M and N (WGM*WGN waves, 64 lanes each)
 // EPT    consecutive elements one thread copies per run (a multiple of 2)
 // DBUF   two LDS stages (1) or one (0)
-// OCC    minimum waves per SIMD the register allocation must allow (0: no limit)
 // ALIGN  A and B rows start on 2-element boundaries (even leading dimensions and
 //        aligned base pointers): full runs use 2-element vector loads; otherwise
 //        every element is loaded alone.
-template <typename T, int BM, int BN, int BK, int WGM, int WGN, int EPT, int DBUF, int OCC,
-          bool ALIGN>
-__global__ void __launch_bounds__(64 * WGM * WGN)
-__attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1)))
-gemm_tiled_kernel(GemmArgs p) {
+template <typename T, int BM, int BN, int BK, int DBUF>
+struct TileLds {
+    static constexpr int SA = BK + 2;                               // A row stride
+    static constexpr int SB = BN + (sizeof(T) == 8 ? 8 : 16);       // B row stride
+    static constexpr int STAGES = DBUF ? 2 : 1;
+    static constexpr int A_ELEMS = STAGES * BM * SA;
+    static constexpr int B_ELEMS = STAGES * BK * SB;
+};
+
+// One BM x BN tile of C at (m0, n0): the whole k-loop and the epilogue.  sAbase
+// and sBbase are the work-group's LDS stages (TileLds sizes); the function ends
+// with a barrier after the last read of LDS, so a caller may reuse the stages
+// for another tile right away.
+template <typename T, int BM, int BN, int BK, int WGM, int WGN, int EPT, int DBUF, bool ALIGN>
+__device__ __forceinline__ void tile_gemm(const GemmArgs &p, int64_t m0, int64_t n0, T *sAbase,
+                                          T *sBbase) {
     typedef Elem<T> E;
     typedef typename E::vec2 vec2;
     typedef typename E::acc4 acc4;
@@ -106,21 +116,14 @@ gemm_tiled_kernel(GemmArgs p) {
     static_assert(B_RUNS >= 1 && B_RUNS * EPT * NT == BK * BN, "B tile split");
     static_assert(A_RUNS_PER_ROW >= 1 && B_RUNS_PER_ROW >= 1, "EPT wider than a tile row");
 
-    __shared__ __attribute__((aligned(16))) T sA[STAGES][BM * SA];
-    __shared__ __attribute__((aligned(16))) T sB[STAGES][BK * SB];
+    T (*sA)[BM * SA] = reinterpret_cast<T (*)[BM * SA]>(sAbase);
+    T (*sB)[BK * SB] = reinterpret_cast<T (*)[BK * SB]>(sBbase);
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
     const int wm = wave / WGN;             // wave position in the work-group grid
     const int wn = wave % WGN;
-
-    const int tiles_m = (int)((p.m + BM - 1) / BM);
-    const int tiles_n = (int)((p.n + BN - 1) / BN);
-    int tm, tn;
-    tile_of_block(blockIdx.x, gridDim.x, tiles_m, tiles_n, tm, tn);
-    const int64_t m0 = (int64_t)tm * BM;
-    const int64_t n0 = (int64_t)tn * BN;
 
     const T *__restrict__ A = (const T *)p.A;
     const T *__restrict__ B = (const T *)p.B;
@@ -277,6 +280,76 @@ gemm_tiled_kernel(GemmArgs p) {
 }
 
 // ---------------------------------------------------------------------------
+// Kernels.
+// ---------------------------------------------------------------------------
+// OCC    minimum waves per SIMD the register allocation must allow (0: no limit)
+
+// One GEMM: one work-group per C tile.
+template <typename T, int BM, int BN, int BK, int WGM, int WGN, int EPT, int DBUF, int OCC,
+          bool ALIGN>
+__global__ void __launch_bounds__(64 * WGM * WGN)
+__attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1)))
+gemm_tiled_kernel(GemmArgs p) {
+    typedef TileLds<T, BM, BN, BK, DBUF> L;
+    __shared__ __attribute__((aligned(16))) T sA[L::A_ELEMS];
+    __shared__ __attribute__((aligned(16))) T sB[L::B_ELEMS];
+    const int tiles_m = (int)((p.m + BM - 1) / BM);
+    const int tiles_n = (int)((p.n + BN - 1) / BN);
+    int tm, tn;
+    tile_of_block(blockIdx.x, gridDim.x, tiles_m, tiles_n, tm, tn);
+    tile_gemm<T, BM, BN, BK, WGM, WGN, EPT, DBUF, ALIGN>(p, (int64_t)tm * BM, (int64_t)tn * BN,
+                                                          sA, sB);
+}
+
+// Many GEMMs sharing one configuration: a persistent grid whose work-groups take
+// tile numbers from an atomic counter until the work list is exhausted.  Tiles
+// are numbered problem by problem (BatchProblem::tile0 is the first number of a
+// problem; the problems are ordered by decreasing work), and the problem of a
+// tile is found by binary search.  Every work-group leaves the loop once the
+// counter passes the total.
+template <typename T, int BM, int BN, int BK, int WGM, int WGN, int EPT, int DBUF, int OCC,
+          bool ALIGN>
+__global__ void __launch_bounds__(64 * WGM * WGN)
+__attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1)))
+gemm_batched_kernel(const BatchProblem *__restrict__ probs, int nprob, int64_t total_tiles,
+                    unsigned long long *counter) {
+    typedef TileLds<T, BM, BN, BK, DBUF> L;
+    __shared__ __attribute__((aligned(16))) T sA[L::A_ELEMS];
+    __shared__ __attribute__((aligned(16))) T sB[L::B_ELEMS];
+    __shared__ int64_t next;
+    for (;;) {
+        if (threadIdx.x == 0) next = (int64_t)atomicAdd(counter, 1ull);
+        __syncthreads();
+        // the tile number is uniform: keep it (and all that follows from it) in
+        // scalar registers
+        const uint64_t tv = (uint64_t)next;
+        const int64_t t = (int64_t)(((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(tv >> 32))
+                                     << 32) |
+                                    (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)tv));
+        __syncthreads();
+        if (t >= total_tiles) break;
+        int lo = 0, hi = nprob - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (probs[mid].tile0 <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        // copy the (uniform) descriptor word by word into scalar registers
+        BatchProblem bp;
+        {
+            const uint32_t *src = reinterpret_cast<const uint32_t *>(probs + lo);
+            uint32_t *dst = reinterpret_cast<uint32_t *>(&bp);
+#pragma unroll
+            for (int w = 0; w < (int)(sizeof(BatchProblem) / 4); ++w)
+                dst[w] = __builtin_amdgcn_readfirstlane(src[w]);
+        }
+        const int64_t local = t - bp.tile0;
+        const int64_t tm = local / bp.tiles_n, tn = local - tm * bp.tiles_n;
+        tile_gemm<T, BM, BN, BK, WGM, WGN, EPT, DBUF, ALIGN>(bp.g, tm * BM, tn * BN, sA, sB);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Launchers and registries.
 // ---------------------------------------------------------------------------
 template <typename T, int BM, int BN, int BK, int WGM, int WGN, int EPT, int DBUF, int OCC,
@@ -290,10 +363,36 @@ hipError_t launch_tiled(const GemmArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <typename T, int BM, int BN, int BK, int WGM, int WGN, int EPT, int DBUF, int OCC,
+          bool ALIGN>
+hipError_t launch_batched(const BatchProblem *probs, int nprob, int64_t total_tiles,
+                          unsigned long long *counter, int grid, hipStream_t s) {
+    hipLaunchKernelGGL((gemm_batched_kernel<T, BM, BN, BK, WGM, WGN, EPT, DBUF, OCC, ALIGN>),
+                       dim3((unsigned)grid), dim3(64 * WGM * WGN), 0, s, probs, nprob, total_tiles,
+                       counter);
+    return hipGetLastError();
+}
+
+// Resident work-groups per compute unit of the batched kernel (occupancy query).
+template <typename T, int BM, int BN, int BK, int WGM, int WGN, int EPT, int DBUF, int OCC,
+          bool ALIGN>
+int batched_occupancy() {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &nb, gemm_batched_kernel<T, BM, BN, BK, WGM, WGN, EPT, DBUF, OCC, ALIGN>,
+            64 * WGM * WGN, 0) != hipSuccess)
+        return 1;
+    return nb > 0 ? nb : 1;
+}
+
 #define MGEMM_CFG(T, BM, BN, BK, WGM, WGN, EPT, DBUF, OCC)                              \
     {{BM, BN, BK, WGM * WGN, EPT, DBUF, OCC},                                             \
      &launch_tiled<T, BM, BN, BK, WGM, WGN, EPT, DBUF, OCC, true>,                        \
-     &launch_tiled<T, BM, BN, BK, WGM, WGN, EPT, DBUF, OCC, false>}
+     &launch_tiled<T, BM, BN, BK, WGM, WGN, EPT, DBUF, OCC, false>,                       \
+     {&launch_batched<T, BM, BN, BK, WGM, WGN, EPT, DBUF, OCC, true>,                     \
+      &launch_batched<T, BM, BN, BK, WGM, WGN, EPT, DBUF, OCC, false>},                   \
+     {&batched_occupancy<T, BM, BN, BK, WGM, WGN, EPT, DBUF, OCC, true>,                  \
+      &batched_occupancy<T, BM, BN, BK, WGM, WGN, EPT, DBUF, OCC, false>}}
 
 static const KernelEntry kF64[] = {
     MGEMM_CFG(double, 128, 128, 16, 2, 2, 2, 1, 0),

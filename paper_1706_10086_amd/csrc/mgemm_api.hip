@@ -161,6 +161,33 @@ static bool aligned_rows(const void *p, int64_t ld, size_t es) {
     return ((uintptr_t)p % (2 * es)) == 0 && (ld % 2) == 0;
 }
 
+// Whether A and B rows start on 2-element boundaries (the vector-load kernels).
+bool rows_aligned(const void *A, int64_t lda, const void *B, int64_t ldb, int32_t dtype) {
+    const size_t es = elem_size(dtype);
+    return aligned_rows(A, lda, es) && aligned_rows(B, ldb, es);
+}
+
+// The registered kernel for (dtype, cfg), or the built-in choice for an m x n
+// output when cfg is NULL.  On failure returns NULL with *err set (-13: cfg not
+// registered; MGEMM_ERR_NOCONFIG: nothing registered).
+const KernelEntry *choose_entry(int32_t dtype, int64_t m, int64_t n, const mgemm_cfg *cfg,
+                                int32_t *err) {
+    int cnt = 0;
+    const KernelEntry *reg = registry(dtype, &cnt);
+    *err = 0;
+    if (cfg) {
+        const KernelEntry *e = find_entry(reg, cnt, *cfg);
+        if (!e)
+            *err = set_error(-13, "configuration %dx%dx%d w%d e%d d%d o%d is not registered",
+                             cfg->bm, cfg->bn, cfg->bk, cfg->waves, cfg->elems_per_thread,
+                             cfg->double_buffer, cfg->occupancy);
+        return e;
+    }
+    const KernelEntry *e = default_entry(dtype, reg, cnt, m, n);
+    if (!e) *err = set_error(MGEMM_ERR_NOCONFIG, "no configuration for dtype %d", dtype);
+    return e;
+}
+
 int32_t split_gemm(const GemmArgs &a, int32_t dtype, hipStream_t s);
 
 }  // namespace mgemm
@@ -185,21 +212,10 @@ int32_t gemm_ex(int64_t m, int64_t n, int64_t k, double alpha, const void *A, in
         if (cfg) return set_error(-13, "split dtypes take no tile configuration");
         return split_gemm(a, dtype, s);
     }
-    int cnt = 0;
-    const KernelEntry *reg = registry(dtype, &cnt);
-    const KernelEntry *e = nullptr;
-    if (cfg) {
-        e = find_entry(reg, cnt, *cfg);
-        if (!e)
-            return set_error(-13, "configuration %dx%dx%d w%d e%d d%d o%d is not registered",
-                             cfg->bm, cfg->bn, cfg->bk, cfg->waves, cfg->elems_per_thread,
-                             cfg->double_buffer, cfg->occupancy);
-    } else {
-        e = default_entry(dtype, reg, cnt, m, n);
-        if (!e) return set_error(MGEMM_ERR_NOCONFIG, "no configuration for dtype %d", dtype);
-    }
-    const size_t es = elem_size(dtype);
-    const bool al = aligned_rows(A, lda, es) && aligned_rows(B, ldb, es);
+    int32_t err = 0;
+    const KernelEntry *e = choose_entry(dtype, m, n, cfg, &err);
+    if (!e) return err;
+    const bool al = rows_aligned(A, lda, B, ldb, dtype);
     hipError_t he = (al ? e->launch : e->launch_unaligned)(a, s);
     if (he != hipSuccess) return hip_error(he, "gemm launch");
     return 0;

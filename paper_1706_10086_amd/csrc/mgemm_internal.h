@@ -20,15 +20,28 @@ struct GemmArgs {
     int64_t ldc;
 };
 
-// A registered kernel: its configuration and its launcher.
+// One problem of a batched launch.  tile0 is the number of the problem's first
+// C tile in the launch's work list; tiles_n the tile columns of the problem.
+struct BatchProblem {
+    GemmArgs g;
+    int64_t tile0;
+    int64_t tiles_n;
+};
+
+// A registered kernel: its configuration and its launchers.  Index [0] of the
+// batched pairs is the variant for rows starting on 2-element boundaries (even
+// leading dimensions, aligned base pointers), [1] the variant for any rows.
 typedef hipError_t (*LaunchFn)(const GemmArgs &, hipStream_t);
+typedef hipError_t (*BatchLaunchFn)(const BatchProblem *, int, int64_t, unsigned long long *, int,
+                                    hipStream_t);
+typedef int (*OccupancyFn)();
 
 struct KernelEntry {
     mgemm_cfg cfg;
-    LaunchFn launch;
-    // true when the kernel needs 16-byte aligned A/B rows (even leading dims and
-    // aligned base pointers for 8-byte elements)
-    LaunchFn launch_unaligned;
+    LaunchFn launch;             // aligned rows
+    LaunchFn launch_unaligned;   // any rows
+    BatchLaunchFn batched[2];
+    OccupancyFn batched_occupancy[2];
 };
 
 // Per-dtype registries, defined in the kernel files.
