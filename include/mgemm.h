@@ -157,6 +157,50 @@ MGEMM_API int32_t gemm_batched_plan_destroy(void *plan);
 MGEMM_API int32_t gemm_batched_plan_info(void *plan, int32_t *buckets, int64_t *total_tiles,
                                          double *flops);
 
+/*
+ * The learned tile-configuration cost model: a 3-layer FP32 MLP
+ *   h1 = relu(W1 x + b1), h2 = relu(W2 h1 + b2), y = W3 h2 + b3
+ * trained with the masked mean square loss sum M (y - t)^2 / sum M and Adam
+ * (Kingma and Ba, ICLR 2015), entirely by the library's HIP kernels.  The paper
+ * hopes its tuning parameters enable automatic tuning (Sec. 1.1) and finds that
+ * tuning itself becomes a compute-intensive task as parameters are added
+ * (Sec. 6); the model predicts a configuration instead of measuring all.
+ *
+ * Parameters are one flat FP32 vector W1 (hidden x in), b1, W2 (hidden x hidden),
+ * b2, W3 (out x hidden), b3, row-major.  Host arrays are marked (host), the rest
+ * are device pointers.  All calls run on the library's current stream and return
+ * after it has finished.  Dimensions are limited to 1..256.
+ */
+/* Creates a model with the given initial parameters (host, mlp_param_count
+ * floats); Adam moments start at zero.  *mlp receives the handle. */
+MGEMM_API int32_t mlp_create(int32_t in_dim, int32_t hidden, int32_t out_dim,
+                             const float *init_params, void **mlp);
+/* Number of parameters (-1 for a NULL handle). */
+MGEMM_API int64_t mlp_param_count(void *mlp);
+/* Copies the parameters in (host) and resets the Adam state. */
+MGEMM_API int32_t mlp_set_params(void *mlp, const float *params);
+/* Copies the parameters out (host). */
+MGEMM_API int32_t mlp_get_params(void *mlp, float *params);
+/* Sets the training set: X rows x in, targets T and mask M rows x out (device;
+ * copied into library buffers). */
+MGEMM_API int32_t mlp_set_data(void *mlp, int64_t rows, const float *X, const float *T,
+                               const float *M);
+/* Loss and gradient (host outputs, either may be NULL) on the training set,
+ * without an update. */
+MGEMM_API int32_t mlp_loss_grad(void *mlp, float *loss, float *grad);
+/* steps full-batch Adam steps (one captured HIP graph per step); *last_loss
+ * (host, may be NULL) receives the loss evaluated in the last step. */
+MGEMM_API int32_t mlp_train(void *mlp, int32_t steps, float lr, float beta1, float beta2,
+                            float eps, float *last_loss);
+/* Y (rows x out) = network(X) (device). */
+MGEMM_API int32_t mlp_forward(void *mlp, int64_t rows, const float *X, float *Y);
+/* idx[r] = argmax over c with M[r,c] != 0 of network(X)[r,c] (lowest index on
+ * ties, -1 when no entry is allowed); X, M, idx device. */
+MGEMM_API int32_t mlp_predict(void *mlp, int64_t rows, const float *X, const float *M,
+                              int32_t *idx);
+/* Frees the model (NULL is a no-op). */
+MGEMM_API int32_t mlp_destroy(void *mlp);
+
 /* Sets the stream used when a call passes NULL; returns 0. */
 MGEMM_API int32_t mgemm_set_stream(void *stream);
 

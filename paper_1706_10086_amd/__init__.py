@@ -290,3 +290,108 @@ class BatchedPlan:
             self.destroy()
         except Exception:
             pass
+
+
+MLP_SYMBOLS = ["mlp_create", "mlp_param_count", "mlp_set_params", "mlp_get_params",
+               "mlp_set_data", "mlp_loss_grad", "mlp_train", "mlp_forward", "mlp_predict",
+               "mlp_destroy"]
+EXPORTED += MLP_SYMBOLS
+
+
+def _mlp_lib():
+    L = lib()
+    if getattr(L, "_mlp_ready", False):
+        return L
+    i64, i32, p, f = ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_float
+    L.mlp_create.argtypes = [i32, i32, i32, p, ctypes.POINTER(p)]
+    L.mlp_param_count.argtypes = [p]
+    L.mlp_param_count.restype = i64
+    L.mlp_set_params.argtypes = [p, p]
+    L.mlp_get_params.argtypes = [p, p]
+    L.mlp_set_data.argtypes = [p, i64, p, p, p]
+    L.mlp_loss_grad.argtypes = [p, p, p]
+    L.mlp_train.argtypes = [p, i32, f, f, f, f, p]
+    L.mlp_forward.argtypes = [p, i64, p, p]
+    L.mlp_predict.argtypes = [p, i64, p, p, p]
+    L.mlp_destroy.argtypes = [p]
+    for n in ("mlp_create", "mlp_set_params", "mlp_get_params", "mlp_set_data", "mlp_loss_grad",
+              "mlp_train", "mlp_forward", "mlp_predict", "mlp_destroy"):
+        getattr(L, n).restype = i32
+    L._mlp_ready = True
+    return L
+
+
+class MLP:
+    """The library's FP32 MLP cost model (see mlp_* in mgemm.h).  Parameters are
+    exchanged as flat float32 numpy arrays; data as float32 torch tensors."""
+
+    def __init__(self, in_dim: int, hidden: int, out_dim: int, init_params):
+        import numpy as np
+        L = _mlp_lib()
+        self.dims = (in_dim, hidden, out_dim)
+        init = np.ascontiguousarray(init_params, dtype=np.float32)
+        self.handle = ctypes.c_void_p()
+        _check(L.mlp_create(in_dim, hidden, out_dim, init.ctypes.data, ctypes.byref(self.handle)))
+        if L.mlp_param_count(self.handle) != init.size:
+            raise ValueError("initial parameter vector has the wrong length")
+
+    @property
+    def n_params(self) -> int:
+        return int(_mlp_lib().mlp_param_count(self.handle))
+
+    def get_params(self):
+        import numpy as np
+        out = np.zeros(self.n_params, dtype=np.float32)
+        _check(_mlp_lib().mlp_get_params(self.handle, out.ctypes.data))
+        return out
+
+    def set_params(self, params) -> None:
+        import numpy as np
+        a = np.ascontiguousarray(params, dtype=np.float32)
+        _check(_mlp_lib().mlp_set_params(self.handle, a.ctypes.data))
+
+    def set_data(self, X, T, M) -> None:
+        self._data = tuple(t.contiguous().float() for t in (X, T, M))
+        X, T, M = self._data
+        _check(_mlp_lib().mlp_set_data(self.handle, X.shape[0], X.data_ptr(), T.data_ptr(),
+                                       M.data_ptr()))
+
+    def loss_grad(self):
+        import numpy as np
+        loss = ctypes.c_float()
+        g = np.zeros(self.n_params, dtype=np.float32)
+        _check(_mlp_lib().mlp_loss_grad(self.handle, ctypes.byref(loss), g.ctypes.data))
+        return loss.value, g
+
+    def train(self, steps: int, lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999,
+              eps: float = 1e-8) -> float:
+        loss = ctypes.c_float()
+        _check(_mlp_lib().mlp_train(self.handle, steps, lr, beta1, beta2, eps, ctypes.byref(loss)))
+        return loss.value
+
+    def forward(self, X):
+        import torch
+        X = X.contiguous().float()
+        Y = torch.empty((X.shape[0], self.dims[2]), device=X.device, dtype=torch.float32)
+        _check(_mlp_lib().mlp_forward(self.handle, X.shape[0], X.data_ptr(), Y.data_ptr()))
+        return Y
+
+    def predict(self, X, M):
+        import torch
+        X = X.contiguous().float()
+        M = M.contiguous().float()
+        idx = torch.empty((X.shape[0],), device=X.device, dtype=torch.int32)
+        _check(_mlp_lib().mlp_predict(self.handle, X.shape[0], X.data_ptr(), M.data_ptr(),
+                                      idx.data_ptr()))
+        return idx
+
+    def destroy(self) -> None:
+        if self.handle:
+            _mlp_lib().mlp_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

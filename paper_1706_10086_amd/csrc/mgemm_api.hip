@@ -17,6 +17,8 @@ namespace mgemm {
 static thread_local std::string g_err;
 static hipStream_t g_stream = nullptr;
 
+hipStream_t current_stream() { return g_stream; }
+
 int32_t set_error(int32_t code, const char *fmt, ...) {
     char buf[512];
     va_list ap;
