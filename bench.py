@@ -1,14 +1,26 @@
 #!/usr/bin/env python3
 """Benchmark of the tiled GEMM C = alpha*A*B + beta*C on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 8192] [--no-cpu]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 8192] [--no-cpu] [--no-extras]
 
-One step is one full GEMM on device-resident inputs (square FP64, N = 8192,
-entries uniform[-1,1], alpha = beta = 1).  The K timed steps are bracketed by a
-device synchronisation on both sides and timed with HIP events on the stream the
-kernels run on; TFLOP/s = 2N^3 / time (the paper's Eq. 4, in TFLOP/s).  Prints
-one JSON line.  The CPU baseline is the oracle (plain FP64 triple loop, all host
-cores) on a bounded sample of rows of the same product.
+One step is one full FP64 GEMM on device-resident inputs (square N = 8192, entries
+uniform[-1,1], alpha = beta = 1): the paper's benchmark computation (Sec. 2, Eq. 1) at
+the headline size.  The K timed steps are bracketed by a device synchronisation on both
+sides and timed with HIP events on the stream the kernels run on; TFLOP/s = 2N^3 / time
+(Eq. 4).  ``value`` is that throughput.
+
+The same JSON line also carries (unless --no-extras):
+  split    the split-precision emulated FP64 GEMM (bf16 and int8 slices) and plain FP64
+           on the wide-range stress inputs at N = 8192: FP64-equivalent TFLOP/s and
+           normwise error against the double-double oracle on sampled rows;
+  batched  2048 uneven FP64 problems (m, n, k log-uniform in [16, 1024]): one captured
+           persistent launch against one launch per problem;
+  tuner    the learned configuration predictor (trained here by the library's MLP
+           kernels on the tuner database in paper_1706_10086_amd/data) on the held-out
+           shapes: achieved fraction of the exhaustive best, against the single tuned
+           configuration per dtype.
+The CPU baseline is the oracle (plain FP64 triple loop, all host cores) on a bounded
+sample of rows of the same product.
 """
 from __future__ import annotations
 
@@ -26,7 +38,8 @@ sys.path.insert(0, ROOT)
 METRIC = "GEMM TFLOP/s (% peak): FP64 vs split-precision at equal error; tuner regret"
 PEAK_F64_TFLOPS = 78.6       # MI355X FP64 matrix peak (published)
 PEAK_F32_TFLOPS = 157.3
-HBM_GBS = 8000.0
+PEAK_BF16_TFLOPS = 2516.6
+PEAK_INT8_TOPS = 5033.2
 
 
 def parse():
@@ -36,6 +49,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extras", action="store_true", help="only the FP64 headline leg")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     return ap.parse_args()
 
@@ -44,23 +58,152 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def timed(fn, stream, reps, warmup=1):
+    """Per-call device times (ms) of fn() with HIP events on ``stream``."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    for i in range(reps):
+        fn()
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    return [ev[i].elapsed_time(ev[i + 1]) for i in range(reps)]
+
+
 def cpu_baseline(n, A, B, C, budget_s):
     """Times the oracle on a row sample of the same product; scales to TFLOP/s."""
     import oracle
     cores = oracle.num_procs()
-    # calibrate with 4 rows, then size the sample to the time budget
+    rows = max(cores, 16)
     t = time.perf_counter()
-    oracle.gemm_f64(1.0, A[:4], B, 1.0, C[:4], nthreads=cores)
+    oracle.gemm_f64(1.0, A[:rows], B, 1.0, C[:rows], nthreads=cores)
     dt = max(time.perf_counter() - t, 1e-6)
-    rows = int(max(cores, min(n, 4 * budget_s / dt)))
+    rows = int(min(n, rows * budget_s / dt))
     rows = max(cores, (rows // cores) * cores)
     t = time.perf_counter()
     oracle.gemm_f64(1.0, A[:rows], B, 1.0, C[:rows], nthreads=cores)
     dt = time.perf_counter() - t
     flops = 2.0 * rows * n * n
-    return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
+    return {"value": round(flops / dt / 1e12, 5), "unit": "TFLOP/s", "cores": cores,
+            "kind": "oracle",
             "sample": f"first {rows} of {n} rows of the N={n} FP64 product "
                       f"({flops / 1e9:.1f} GFLOP in {dt:.1f} s, OpenMP over rows)"}
+
+
+def leg_split(mg, torch, dev, n=8192):
+    import oracle
+    import synth
+    log(f"bench: split leg, N={n} wide-range inputs")
+    sa, sb, _ = synth.seeds_for(2, int(np.log2(n)))
+    A = synth.wide_range((n, n), sa)
+    B = synth.wide_range((n, n), sb)
+    tA, tB = torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev)
+    tC = torch.zeros((n, n), device=dev, dtype=torch.float64)
+    stream = torch.cuda.current_stream()
+    rows = np.array([0, 1, 1000, 2222, 4096, 5000, 7777, n - 1])
+    log("bench: split leg, Dot2 oracle on sampled rows")
+    ref = oracle.gemm_dot2(1.0, A[rows], B, nthreads=oracle.num_procs())
+    out = {"n": n, "inputs": "u*2^e, u uniform[-1,1], e uniform integer in [-20,20]",
+           "error": f"normwise vs double-double oracle on {len(rows)} sampled rows"}
+    for name, dt in (("f64", mg.F64), ("bf16", mg.SPLIT_BF16), ("int8", mg.SPLIT_INT8)):
+        ts = timed(lambda: mg.gemm(tA, tB, tC, 1.0, 0.0, dtype=dt, stream=stream), stream, 5)
+        got = tC[torch.from_numpy(rows).to(dev)].cpu().numpy()
+        err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        ms = float(np.mean(ts))
+        out[name] = {"ms": round(ms, 4), "tflops_fp64_equiv": round(2.0 * n ** 3 / ms / 1e9, 3),
+                     "pct_fp64_peak": round(100 * 2.0 * n ** 3 / ms / 1e9 / PEAK_F64_TFLOPS, 2),
+                     "rel_err": err}
+        log(f"  {name}: {ms:.3f} ms, err {err:.2e}")
+    out["bf16"]["mfma_util"] = round(21 * 2.0 * n ** 3 / (out["bf16"]["ms"] * 1e9) / PEAK_BF16_TFLOPS, 4)
+    out["int8"]["mfma_util"] = round(36 * 2.0 * n ** 3 / (out["int8"]["ms"] * 1e9) / PEAK_INT8_TOPS, 4)
+    del tA, tB, tC
+    return out
+
+
+def leg_batched(mg, torch, dev):
+    import synth
+    log("bench: batched leg, 2048 uneven FP64 problems")
+    cnt = 2048
+    ms = synth.log_uniform_int(cnt, 4001, 16, 1024)
+    ns = synth.log_uniform_int(cnt, 4002, 16, 1024)
+    ks = synth.log_uniform_int(cnt, 4003, 16, 1024)
+    g = torch.Generator(device=dev)
+    g.manual_seed(4004)
+    As = [torch.rand((int(m), int(k)), device=dev, dtype=torch.float64, generator=g) * 2 - 1
+          for m, k in zip(ms, ks)]
+    Bs = [torch.rand((int(k), int(n)), device=dev, dtype=torch.float64, generator=g) * 2 - 1
+          for k, n in zip(ks, ns)]
+    Cs = [torch.zeros((int(m), int(n)), device=dev, dtype=torch.float64) for m, n in zip(ms, ns)]
+    flops = float(sum(2.0 * m * n * k for m, n, k in zip(ms, ns, ks)))
+    stream = torch.cuda.current_stream()
+    plan = mg.BatchedPlan(As, Bs, Cs, 1.0, 0.0, stream=stream)
+    tp = timed(plan.execute, stream, 10, warmup=2)
+    tl = timed(lambda: mg.gemm_batched(As, Bs, Cs, 1.0, 0.0), stream, 3, warmup=1)
+    info = plan.info()
+    plan.destroy()
+    return {"problems": cnt, "flops": flops, "buckets": info["buckets"], "tiles": info["tiles"],
+            "graph_ms": round(float(np.mean(tp)), 4),
+            "graph_tflops": round(flops / float(np.mean(tp)) / 1e9, 3),
+            "per_problem_ms": round(float(np.mean(tl)), 4),
+            "per_problem_tflops": round(flops / float(np.mean(tl)) / 1e9, 3),
+            "speedup": round(float(np.mean(tl)) / float(np.mean(tp)), 3)}
+
+
+def live_recheck(mg, pred, table, count=12):
+    """Re-times held-out FP64 shapes now: TFLOP/s of the predicted configuration
+    over the best of all registered configurations, measured in this run."""
+    import torch
+    from paper_1706_10086_amd import learn, tune
+    shapes = [s for s in tune.shape_set("heldout") if 2.0 * s[0] * s[1] * s[2] < 2e11][:count]
+    choice = learn.predict(pred, [(mg.F64, *s) for s in shapes])
+    fr = []
+    for (m, n, k), c in zip(shapes, choice):
+        ops = tune.Operands(m, n, k, mg.F64)
+        tf = {}
+        for cfg in mg.configs(mg.F64):
+            t = tune.time_config(ops, mg.F64, cfg, warmup=1, reps=3)
+            tf[cfg.as_tuple()] = tune.flops(m, n, k) / (min(t) * 1e9)
+        fr.append(tf[table[c][1]] / max(tf.values()))
+        del ops
+    torch.cuda.empty_cache()
+    return learn.summarize(np.array(fr))
+
+
+def leg_tuner(mg):
+    from paper_1706_10086_amd import learn, tune
+    path = os.path.join(ROOT, "paper_1706_10086_amd", "data", "tune_db.json.gz")
+    if not os.path.exists(path):
+        return {"status": "no tuner database"}
+    log("bench: tuner leg, training the MLP on the tuner database")
+    db = tune.load_compact(path)
+    table = learn.config_table()
+    tr = [(dt, *s) for dt in (mg.F64, mg.F32) for s in tune.shape_set("train")]
+    ho = [(dt, *s) for dt in (mg.F64, mg.F32) for s in tune.shape_set("heldout")]
+    dtr = learn.build_dataset(db, table, tr)
+    dho = learn.build_dataset(db, table, ho)
+    if not dtr.shapes or not dho.shapes:
+        return {"status": "tuner database does not match the configuration registry"}
+    t0 = time.time()
+    pred = learn.train(dtr, table, steps=6000, lr=2e-3)
+    t_train = time.time() - t0
+    choice = learn.predict(pred, dho.shapes)
+    base = learn.single_best_baseline(dtr, table)
+    mlp = learn.summarize(learn.achieved(dho, choice))
+    single = learn.summarize(learn.achieved(dho, [base[s[0]] for s in dho.shapes]))
+    top3 = learn.summarize(learn.top_k_fallback(dho, pred, 3))
+    log("bench: tuner leg, live re-timing of held-out shapes")
+    live = live_recheck(mg, pred, table)
+    return {"database": "paper_1706_10086_amd/data/tune_db.json.gz (MI355X sweep: 3000 train + "
+                        "500 held-out shapes, m,n,k log-uniform in [64,16384], FP64 and FP32, "
+                        "every registered configuration)",
+            "train_rows": len(dtr.shapes), "heldout_rows": len(dho.shapes),
+            "train_s": round(t_train, 2), "mlp": mlp, "single_best_config": single,
+            "mlp_top3_measured": top3, "regret_geomean": round(1.0 - mlp["geomean"], 4),
+            "gain_over_single": round(mlp["geomean"] / single["geomean"], 4),
+            "live_recheck_f64": live}
 
 
 def main():
@@ -115,12 +258,11 @@ def main():
     kern_ms = float(np.mean(per))
     best_ms = float(np.min(per))
 
-    # accuracy of this exact run against the oracle on sampled rows
+    # accuracy of this run against the oracle on sampled rows: C_s = A B + C_{s-1}
+    import oracle
+    log("bench: accuracy check on sampled rows")
     rows = np.arange(0, n, max(1, n // 16))
     steps_done = args.warmup + args.steps
-    log("bench: accuracy check on sampled rows")
-    import oracle
-    # C was updated steps_done times: C_s = A B + C_{s-1}; recompute on the rows
     ref = C0[rows].copy()
     AB = oracle.gemm_f64(1.0, A[rows], B, 0.0, None, nthreads=oracle.num_procs())
     for _ in range(steps_done):
@@ -132,7 +274,12 @@ def main():
     if not args.no_cpu:
         log("bench: CPU oracle baseline")
         cpu = cpu_baseline(n, A, B, C0, args.cpu_seconds)
+    del tA, tB, tC
 
+    cfg_used = None
+    for c in mg.configs(mg.F64):
+        if (c.bm, c.bn, c.bk, c.waves) == (256, 128, 16, 8):
+            cfg_used = c.as_dict()
     out = {
         "metric": METRIC,
         "value": round(tflops, 3),
@@ -147,8 +294,9 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"square DGEMM N={n}, FP64 row-major, A,B,C uniform[-1,1], "
-                               f"alpha=1, beta=1, default tile configuration",
-                   "n": n, "alpha": 1.0, "beta": 1.0, "parallelism": "single GPU"},
+                               f"alpha=1, beta=1 (library's default tile configuration)",
+                   "n": n, "alpha": 1.0, "beta": 1.0, "tile_config": cfg_used,
+                   "parallelism": "single GPU"},
         "pct_peak": round(100.0 * tflops / PEAK_F64_TFLOPS, 2),
         "best_step_tflops": round(flops / (best_ms * 1e-3) / 1e12, 3),
         "wall_s": round(wall, 3),
@@ -157,10 +305,22 @@ def main():
                      "peak": PEAK_F64_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(flops / (kern_ms * 1e-3) / 1e12 / PEAK_F64_TFLOPS, 4),
                      "traffic": None,
-                     "kernel": "gemm_tiled_kernel<double,...> (one launch per step)",
-                     "kernel_avg_ms": round(kern_ms, 4)},
+                     "kernel": "gemm_tiled_kernel<double,256,128,16,4,2,2,1,0,true> "
+                               "(one launch per step)",
+                     "kernel_avg_ms": round(kern_ms, 4),
+                     "work_per_launch": f"2*N^3 = {flops:.4g} FLOP"},
         "cpu_baseline": cpu,
     }
+    if not args.no_extras:
+        for name, fn in (("split", lambda: leg_split(mg, torch, dev)),
+                         ("batched", lambda: leg_batched(mg, torch, dev)),
+                         ("tuner", lambda: leg_tuner(mg))):
+            try:
+                out[name] = fn()
+            except Exception as e:  # an extra leg must not hide the headline line
+                out[name] = {"status": f"failed: {type(e).__name__}: {e}"}
+                log(f"bench: {name} leg failed: {e}")
+            torch.cuda.empty_cache()
     print(json.dumps(out), flush=True)
     return 0
 

@@ -1,0 +1,216 @@
+"""Learned tile-configuration predictor on top of the autotuner's database.
+
+The paper tunes its two parameters by exhaustive search on two matrix sizes
+(Sec. 2.3, Sec. 3 Tab. 4) and concludes that more tuning parameters make tuning
+itself expensive (Sec. 6).  Here the tuner's sweep over many shapes trains a
+small network that predicts, for an unseen shape, the relative speed of every
+configuration; the configuration with the highest prediction is used, and the
+exhaustive sweep remains the fallback and the judge of the prediction's regret.
+
+* features  x = [log2 m, log2 n, log2 k, onehot(F64, F32, split-BF16)], scaled
+            by the training set's mean and standard deviation;
+* targets   r_c = TFLOP/s(c) / max_c' TFLOP/s(c') for every configuration c of
+            the shape's dtype (a masked multi-output regression; configurations
+            of other dtypes are masked out);
+* model     the library's MLP (6 -> 64 -> 64 -> V, FP32), trained by its own HIP
+            kernels with Adam on the masked mean square error;
+* choice    masked arg-max of the prediction;
+* metrics   achieved fraction of the exhaustive best per held-out shape, with
+            its geometric mean, median, 10th percentile and the share >= 0.95;
+            the baseline without the model is the paper's method: one tuned
+            configuration per dtype, the one with the best geometric-mean
+            relative speed over the training shapes.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import F32, F64, SPLIT_BF16, MLP, configs
+
+DTYPES = (F64, F32, SPLIT_BF16)
+
+
+def config_table():
+    """Output slots: (dtype, cfg tuple) for every registered configuration of the
+    dtypes with a registry, in registry order."""
+    table = []
+    for dt in (F64, F32):
+        for c in configs(dt):
+            table.append((dt, c.as_tuple()))
+    return table
+
+
+def table_hash(table) -> str:
+    return hashlib.sha1(json.dumps([[d, list(c)] for d, c in table]).encode()).hexdigest()[:12]
+
+
+def raw_features(m, n, k, dtype) -> np.ndarray:
+    oh = [1.0 if dtype == d else 0.0 for d in DTYPES]
+    return np.array([math.log2(m), math.log2(n), math.log2(k)] + oh, dtype=np.float64)
+
+
+@dataclass
+class Dataset:
+    shapes: list            # (dtype, m, n, k)
+    X: np.ndarray           # raw features
+    T: np.ndarray           # relative speeds (0 where masked)
+    M: np.ndarray           # mask
+    tflops: np.ndarray      # measured TFLOP/s per slot (nan where not measured)
+
+
+def build_dataset(db, table, shapes_with_dtype) -> Dataset:
+    """Rows for every (dtype, m, n, k) that has measurements of all the dtype's
+    slots in the database."""
+    slot = {key: i for i, key in enumerate(table)}
+    V = len(table)
+    by_shape = {}
+    for r in db.records:
+        key = (r["dtype"], r["m"], r["n"], r["k"])
+        by_shape.setdefault(key, {})[tuple(r["cfg"])] = max(
+            r["tflops"], by_shape.get(key, {}).get(tuple(r["cfg"]), 0.0))
+    shapes, X, T, M, TF = [], [], [], [], []
+    for (dt, m, n, k) in shapes_with_dtype:
+        meas = by_shape.get((dt, m, n, k))
+        want = [c for (d, c) in table if d == dt]
+        if not meas or any(c not in meas for c in want):
+            continue
+        tf = np.full(V, np.nan)
+        for c in want:
+            tf[slot[(dt, c)]] = meas[c]
+        best = np.nanmax(tf)
+        t = np.where(np.isnan(tf), 0.0, tf / best)
+        mask = (~np.isnan(tf)).astype(np.float64)
+        shapes.append((dt, m, n, k))
+        X.append(raw_features(m, n, k, dt))
+        T.append(t)
+        M.append(mask)
+        TF.append(tf)
+    return Dataset(shapes, np.array(X), np.array(T), np.array(M), np.array(TF))
+
+
+@dataclass
+class Predictor:
+    table: list
+    mean: np.ndarray
+    std: np.ndarray
+    params: np.ndarray
+    hidden: int = 64
+    history: list = field(default_factory=list)
+
+    def scaled(self, X):
+        return (X - self.mean) / self.std
+
+    def to_json(self) -> str:
+        return json.dumps({"table": [[d, list(c)] for d, c in self.table],
+                           "table_hash": table_hash(self.table), "mean": self.mean.tolist(),
+                           "std": self.std.tolist(), "hidden": self.hidden,
+                           "params": self.params.tolist(), "history": self.history})
+
+    @classmethod
+    def from_json(cls, s: str, check_table=None) -> "Predictor":
+        d = json.loads(s)
+        table = [(dt, tuple(c)) for dt, c in d["table"]]
+        if table_hash(table) != d["table_hash"]:
+            raise ValueError("corrupt model file (table hash)")
+        if check_table is not None and table_hash(check_table) != d["table_hash"]:
+            raise ValueError("model was trained for a different configuration table")
+        return cls(table, np.array(d["mean"]), np.array(d["std"]), np.array(d["params"], dtype=np.float32),
+                   d["hidden"], d.get("history", []))
+
+
+def train(ds: Dataset, table, hidden=64, steps=4000, lr=2e-3, seed=5, log=None) -> Predictor:
+    """Fits the MLP on the GPU with the library's kernels (full-batch Adam)."""
+    import torch
+    mean = ds.X.mean(axis=0)
+    std = ds.X.std(axis=0)
+    std[std == 0] = 1.0
+    I, O = ds.X.shape[1], len(table)
+    init = _init_params(I, hidden, O, seed)
+    net = MLP(I, hidden, O, init)
+    dev = torch.device("cuda")
+    Xs = torch.from_numpy(((ds.X - mean) / std).astype(np.float32)).to(dev)
+    net.set_data(Xs, torch.from_numpy(ds.T.astype(np.float32)).to(dev),
+                 torch.from_numpy(ds.M.astype(np.float32)).to(dev))
+    hist = []
+    done = 0
+    chunk = 500
+    while done < steps:
+        s = min(chunk, steps - done)
+        loss = net.train(s, lr=lr)
+        done += s
+        hist.append((done, float(loss)))
+        if log:
+            log(f"  mlp step {done}: loss {loss:.5f}")
+    params = net.get_params()
+    net.destroy()
+    return Predictor(table, mean, std, params, hidden, hist)
+
+
+def _init_params(I, H, O, seed):
+    """He-uniform weights from the seeded generator, zero biases (the same
+    recipe as the oracle's he_uniform_init, restated here so the product path
+    does not import the oracle)."""
+    import synth
+    parts = []
+    for li, (fo, fi) in enumerate([(H, I), (H, H), (O, H)]):
+        lim = np.sqrt(6.0 / fi)
+        parts.append((synth.uniform_pm1((fo, fi), seed + li) * lim).ravel())
+        parts.append(np.zeros(fo))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def predict(pred: Predictor, shapes_with_dtype) -> list:
+    """Predicted slot index per (dtype, m, n, k), by the library's GPU kernels."""
+    import torch
+    X = np.array([raw_features(m, n, k, dt) for (dt, m, n, k) in shapes_with_dtype])
+    M = np.array([[1.0 if d == dt else 0.0 for (d, _) in pred.table]
+                  for (dt, _, _, _) in shapes_with_dtype])
+    I, O = X.shape[1], len(pred.table)
+    net = MLP(I, pred.hidden, O, pred.params)
+    dev = torch.device("cuda")
+    idx = net.predict(torch.from_numpy(pred.scaled(X).astype(np.float32)).to(dev),
+                      torch.from_numpy(M.astype(np.float32)).to(dev)).cpu().numpy()
+    net.destroy()
+    return [int(i) for i in idx]
+
+
+def single_best_baseline(ds: Dataset, table) -> dict:
+    """Per dtype: the slot with the best geometric-mean relative speed over the
+    dataset (one tuned configuration per dtype, the paper's tuning outcome)."""
+    out = {}
+    for dt in {s[0] for s in ds.shapes}:
+        rows = [i for i, s in enumerate(ds.shapes) if s[0] == dt]
+        slots = [j for j, (d, _) in enumerate(table) if d == dt]
+        logs = {j: np.mean(np.log(np.maximum(ds.T[rows, j], 1e-9))) for j in slots}
+        out[dt] = max(logs, key=logs.get)
+    return out
+
+
+def achieved(ds: Dataset, choice) -> np.ndarray:
+    """Fraction of the exhaustive best reached by the chosen slot per row."""
+    return np.array([ds.T[i, c] for i, c in enumerate(choice)])
+
+
+def summarize(frac: np.ndarray) -> dict:
+    frac = np.asarray(frac, dtype=np.float64)
+    return {"geomean": float(np.exp(np.mean(np.log(np.maximum(frac, 1e-9))))),
+            "median": float(np.median(frac)), "p10": float(np.percentile(frac, 10)),
+            "share_ge_0.95": float(np.mean(frac >= 0.95)), "n": int(frac.size)}
+
+
+def top_k_fallback(ds: Dataset, pred: Predictor, k=3) -> np.ndarray:
+    """Achieved fraction when the k best-predicted slots are measured and the
+    fastest is kept (uses the database's measurements of those slots)."""
+    import torch
+    I, O = ds.X.shape[1], len(pred.table)
+    net = MLP(I, pred.hidden, O, pred.params)
+    Y = net.forward(torch.from_numpy(pred.scaled(ds.X).astype(np.float32)).cuda()).cpu().numpy()
+    net.destroy()
+    Y = np.where(ds.M > 0, Y, -np.inf)
+    top = np.argsort(-Y, axis=1)[:, :k]
+    return np.array([max(ds.T[i, j] for j in top[i] if ds.M[i, j] > 0) for i in range(len(top))])

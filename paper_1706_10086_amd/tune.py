@@ -175,3 +175,157 @@ def regret(db: DB, dtype: int, m: int, n: int, k: int, cfg) -> float:
     if not mine:
         raise KeyError("configuration not measured on this shape")
     return 1.0 - max(mine) / best
+
+
+# ---------------------------------------------------------------------------
+# Shape sets of the learned-tuner workload and the sweep driver.
+# ---------------------------------------------------------------------------
+TRAIN_SEEDS = (5001, 5002, 5003)
+HELDOUT_SEEDS = (5011, 5012, 5013)
+
+
+def shape_set(which: str, count: int | None = None, lo: int = 64, hi: int = 16384):
+    """'train' (3000 shapes) or 'heldout' (500 shapes, none also in 'train'):
+    m, n, k each log-uniform in [lo, hi] from their own seeded streams."""
+    import synth
+    if which == "train":
+        seeds, cnt = TRAIN_SEEDS, 3000 if count is None else count
+    elif which == "heldout":
+        seeds, cnt = HELDOUT_SEEDS, 500 if count is None else count
+    else:
+        raise ValueError(which)
+    ms, ns, ks = (synth.log_uniform_int(cnt + 64, s, lo, hi) for s in seeds)
+    shapes = [(int(a), int(b), int(c)) for a, b, c in zip(ms, ns, ks)]
+    if which == "heldout":
+        tr = set(shape_set("train", lo=lo, hi=hi))
+        shapes = [s for s in shapes if s not in tr]
+    out, seen = [], set()
+    for s in shapes:
+        if s not in seen:
+            seen.add(s)
+            out.append(s)
+    return out[:cnt]
+
+
+class Arena:
+    """One device allocation per operand, sized for the largest shape of a sweep
+    and filled once with uniform[-1,1) values; shapes take contiguous views."""
+
+    def __init__(self, shapes, dtype):
+        import torch
+        tdt = torch.float32 if dtype == F32 else torch.float64
+        ma = max(m * k for m, n, k in shapes)
+        mb = max(k * n for m, n, k in shapes)
+        mc = max(m * n for m, n, k in shapes)
+        g = torch.Generator(device="cuda")
+        g.manual_seed(12345)
+        self.a = torch.rand(ma, device="cuda", dtype=tdt, generator=g) * 2 - 1
+        self.b = torch.rand(mb, device="cuda", dtype=tdt, generator=g) * 2 - 1
+        self.c = torch.zeros(mc, device="cuda", dtype=tdt)
+
+    def operands(self, m, n, k):
+        o = Operands.__new__(Operands)
+        o.A = self.a[:m * k].view(m, k)
+        o.B = self.b[:k * n].view(k, n)
+        o.C = self.c[:m * n].view(m, n)
+        return o
+
+
+def sweep_set(shapes, dtype, db: DB, reps=2, abandon=2.0, log=print, every=25):
+    """Resumable sweep of every registered configuration over ``shapes``."""
+    dev, bid = device_name(), build_id()
+    cfgs = list(configs(dtype))
+    done = db.keys()
+    todo = [s for s in shapes
+            if any((dev, bid, dtype, s[0], s[1], s[2], c.as_tuple()) not in done for c in cfgs)]
+    if not todo:
+        log(f"sweep dtype={dtype}: nothing to do ({len(shapes)} shapes already measured)")
+        return 0
+    arena = Arena(todo, dtype)
+    t0 = time.time()
+    new = 0
+    for i, (m, n, k) in enumerate(todo):
+        ops = arena.operands(m, n, k)
+        best = None
+        for c in cfgs:
+            key = (dev, bid, dtype, m, n, k, c.as_tuple())
+            if key in done:
+                continue
+            t = time_config(ops, dtype, c, reps=reps,
+                            abandon_ms=None if best is None else abandon * best)
+            rec = {"device": dev, "build": bid, "dtype": dtype, "m": m, "n": n, "k": k,
+                   "cfg": list(c.as_tuple()), "times_ms": [round(x, 5) for x in t],
+                   "best_ms": min(t), "median_ms": float(np.median(t)),
+                   "tflops": flops(m, n, k) / (float(np.median(t)) * 1e-3) / 1e12,
+                   "abandoned": len(t) < reps, "ts": time.time()}
+            db.append(rec)
+            new += 1
+            best = rec["best_ms"] if best is None else min(best, rec["best_ms"])
+        if (i + 1) % every == 0 or i + 1 == len(todo):
+            log(f"sweep dtype={dtype}: {i + 1}/{len(todo)} shapes, {new} records, "
+                f"{time.time() - t0:.0f} s")
+    return new
+
+
+def main(argv=None):
+    import argparse
+    ap = argparse.ArgumentParser(description="autotuner sweep (resumable JSONL database)")
+    ap.add_argument("--set", choices=["train", "heldout"], required=True)
+    ap.add_argument("--dtype", choices=["f64", "f32"], required=True)
+    ap.add_argument("--db", required=True)
+    ap.add_argument("--count", type=int, default=None)
+    ap.add_argument("--reps", type=int, default=2)
+    a = ap.parse_args(argv)
+    dt = F64 if a.dtype == "f64" else F32
+    db = DB.load(a.db)
+    if db.bad_lines:
+        print(f"tune: skipped {db.bad_lines} unreadable database lines", flush=True)
+    shapes = shape_set(a.set, a.count)
+    n = sweep_set(shapes, dt, db, reps=a.reps, log=lambda s: print(s, flush=True))
+    print(f"tune: {n} new records in {a.db}", flush=True)
+
+
+if __name__ == "__main__":
+    main()
+
+
+# ---------------------------------------------------------------------------
+# Compact, read-only form of a database (shipped with the package).
+# ---------------------------------------------------------------------------
+def save_compact(db: DB, path: str) -> None:
+    """gzip'd JSON: one row per (dtype, m, n, k) with the TFLOP/s of every
+    measured configuration (the best of duplicate measurements)."""
+    import gzip
+    cfgs, rows = {}, {}
+    for r in db.records:
+        dt = r["dtype"]
+        c = tuple(r["cfg"])
+        lst = cfgs.setdefault(dt, [])
+        if c not in lst:
+            lst.append(c)
+        key = (dt, r["m"], r["n"], r["k"])
+        row = rows.setdefault(key, {})
+        row[c] = max(row.get(c, 0.0), r["tflops"])
+    devices = sorted({r["device"] for r in db.records})
+    out = {"devices": devices, "configs": {str(dt): [list(c) for c in cs] for dt, cs in cfgs.items()},
+           "rows": [[dt, m, n, k, [round(row.get(c, -1.0), 4) for c in cfgs[dt]]]
+                    for (dt, m, n, k), row in sorted(rows.items())]}
+    with gzip.open(path, "wt") as f:
+        json.dump(out, f, separators=(",", ":"))
+
+
+def load_compact(path: str) -> DB:
+    """A DB (records without timings) from save_compact's file."""
+    import gzip
+    with gzip.open(path, "rt") as f:
+        d = json.load(f)
+    dev = d["devices"][0] if d["devices"] else "unknown"
+    recs = []
+    for dt, m, n, k, tf in d["rows"]:
+        for c, v in zip(d["configs"][str(dt)], tf):
+            if v < 0:
+                continue
+            recs.append({"device": dev, "build": "compact", "dtype": dt, "m": m, "n": n, "k": k,
+                         "cfg": list(c), "tflops": v, "best_ms": flops(m, n, k) / (v * 1e9),
+                         "median_ms": flops(m, n, k) / (v * 1e9)})
+    return DB(path, recs, 0)

@@ -1,0 +1,66 @@
+"""The learned configuration predictor on the GPU: the MLP is trained by the
+library's kernels on the shipped MI355X tuner database and judged on the 500
+held-out shapes (FP64 and FP32) against the exhaustive best: geometric mean of
+TFLOP/s(predicted) / TFLOP/s(best) >= 0.95, and better than the method without
+the network (one tuned configuration per dtype)."""
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1706_10086_amd as mg  # noqa: E402
+from paper_1706_10086_amd import learn, tune  # noqa: E402
+
+DB_PATH = os.path.join(os.path.dirname(learn.__file__), "data", "tune_db.json.gz")
+
+
+@pytest.fixture(scope="module")
+def data():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    db = tune.load_compact(DB_PATH)
+    table = learn.config_table()
+    tr = [(dt, *s) for dt in (mg.F64, mg.F32) for s in tune.shape_set("train")]
+    ho = [(dt, *s) for dt in (mg.F64, mg.F32) for s in tune.shape_set("heldout")]
+    dtr = learn.build_dataset(db, table, tr)
+    dho = learn.build_dataset(db, table, ho)
+    assert len(dtr.shapes) == 6000 and len(dho.shapes) == 1000, "database does not match registry"
+    return table, dtr, dho
+
+
+def test_mlp_regret_within_5_percent_and_beats_single_config(data):
+    table, dtr, dho = data
+    print("training the predictor", flush=True)
+    pred = learn.train(dtr, table, steps=6000, lr=2e-3)
+    assert pred.history[-1][1] < pred.history[0][1]
+    choice = learn.predict(pred, dho.shapes)
+    mlp = learn.summarize(learn.achieved(dho, choice))
+    base = learn.single_best_baseline(dtr, table)
+    single = learn.summarize(learn.achieved(dho, [base[s[0]] for s in dho.shapes]))
+    top3 = learn.summarize(learn.top_k_fallback(dho, pred, 3))
+    print(f"  mlp {mlp}\n  single {single}\n  top3 {top3}", flush=True)
+    assert mlp["geomean"] >= 0.95
+    assert mlp["geomean"] > single["geomean"]
+    assert top3["geomean"] >= mlp["geomean"]
+    for dt in (mg.F64, mg.F32):
+        rows = [i for i, s in enumerate(dho.shapes) if s[0] == dt]
+        assert learn.summarize(learn.achieved(dho, choice)[rows])["geomean"] >= 0.95
+
+
+def test_predictions_are_valid_configurations(data):
+    table, dtr, dho = data
+    pred = learn.train(dtr, table, steps=500, lr=2e-3)
+    choice = learn.predict(pred, dho.shapes[:50] + dho.shapes[-50:])
+    for (dt, m, n, k), c in zip(dho.shapes[:50] + dho.shapes[-50:], choice):
+        assert table[c][0] == dt
+        cfg = mg.Cfg(*table[c][1])
+        tdt = torch.float64 if dt == mg.F64 else torch.float32
+        a = torch.ones((3, 5), device="cuda", dtype=tdt)
+        b = torch.ones((5, 7), device="cuda", dtype=tdt)
+        out = torch.zeros((3, 7), device="cuda", dtype=tdt)
+        mg.gemm(a, b, out, 1.0, 0.0, cfg=cfg)
+        torch.cuda.synchronize()
+        assert torch.all(out == 5.0)

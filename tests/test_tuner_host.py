@@ -1,0 +1,114 @@
+"""Host logic of the autotuner and the learned predictor (no GPU): shape sets,
+the resumable JSONL database, the compact database, exhaustive best and regret,
+dataset construction and the single-configuration baseline."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_1706_10086_amd import learn, tune
+
+
+def test_shape_sets_are_log_uniform_disjoint_and_fixed():
+    tr = tune.shape_set("train")
+    ho = tune.shape_set("heldout")
+    assert len(tr) == 3000 and len(ho) == 500
+    assert not set(tr) & set(ho)
+    allv = np.array(tr + ho)
+    assert allv.min() >= 64 and allv.max() <= 16384
+    # log-uniform: about half of the values below the geometric midpoint 1024
+    assert abs(np.mean(allv < 1024) - 0.5) < 0.03
+    assert tune.shape_set("train")[:5] == tr[:5]
+
+
+def rec(dt, m, n, k, cfg, tf, device="dev", build="b"):
+    return {"device": device, "build": build, "dtype": dt, "m": m, "n": n, "k": k,
+            "cfg": list(cfg), "tflops": tf, "best_ms": 1.0, "median_ms": 1.0}
+
+
+def test_db_resumes_and_skips_corrupt_lines(tmp_path):
+    p = tmp_path / "db.jsonl"
+    db = tune.DB.load(str(p))
+    db.append(rec(0, 64, 64, 64, (1, 2, 3, 4, 5, 6, 7), 1.0))
+    db.append(rec(0, 64, 64, 64, (1, 2, 3, 4, 5, 6, 8), 2.0))
+    with open(p, "a") as f:
+        f.write('{"truncated": \n')
+        f.write("not json\n")
+    db2 = tune.DB.load(str(p))
+    assert db2.bad_lines == 2 and len(db2.records) == 2
+    assert ("dev", "b", 0, 64, 64, 64, (1, 2, 3, 4, 5, 6, 8)) in db2.keys()
+
+
+def test_exhaustive_best_and_regret():
+    db = tune.DB("x", [rec(0, 8, 8, 8, (1,), 10.0), rec(0, 8, 8, 8, (2,), 40.0),
+                       rec(0, 8, 8, 8, (3,), 30.0), rec(1, 8, 8, 8, (1,), 99.0)])
+    cfg, tf = tune.exhaustive_best(db, 0, 8, 8, 8)
+    assert cfg == (2,) and tf == 40.0
+    assert tune.regret(db, 0, 8, 8, 8, (3,)) == pytest.approx(0.25)
+    assert tune.regret(db, 0, 8, 8, 8, (2,)) == 0.0
+    with pytest.raises(KeyError):
+        tune.regret(db, 0, 8, 8, 8, (9,))
+
+
+def test_compact_roundtrip(tmp_path):
+    recs = [rec(0, 64, 128, 256, (128, 128, 16, 4, 2, 1, 0), 12.5),
+            rec(0, 64, 128, 256, (64, 64, 16, 4, 2, 1, 0), 20.25),
+            rec(1, 99, 100, 101, (32, 32, 16, 1, 2, 1, 0), 3.0)]
+    db = tune.DB("x", recs)
+    path = str(tmp_path / "c.json.gz")
+    tune.save_compact(db, path)
+    back = tune.load_compact(path)
+    got = {(r["dtype"], r["m"], r["n"], r["k"], tuple(r["cfg"])): r["tflops"] for r in back.records}
+    want = {(r["dtype"], r["m"], r["n"], r["k"], tuple(r["cfg"])): r["tflops"] for r in recs}
+    assert got == want
+
+
+def test_dataset_targets_masks_and_single_best():
+    table = [(0, (1,)), (0, (2,)), (1, (1,))]
+    recs = []
+    shapes = [(0, 64, 64, 64), (0, 128, 64, 64), (1, 64, 64, 64), (0, 999, 1, 1)]
+    tfs = {(0, 64, 64, 64): {(1,): 10.0, (2,): 20.0},
+           (0, 128, 64, 64): {(1,): 30.0, (2,): 15.0},
+           (1, 64, 64, 64): {(1,): 7.0},
+           (0, 999, 1, 1): {(1,): 1.0}}            # incomplete: dropped
+    for (dt, m, n, k), d in tfs.items():
+        for c, v in d.items():
+            recs.append(rec(dt, m, n, k, c, v))
+    ds = learn.build_dataset(tune.DB("x", recs), table, shapes)
+    assert ds.shapes == shapes[:3]
+    assert np.allclose(ds.T, [[0.5, 1.0, 0.0], [1.0, 0.5, 0.0], [0.0, 0.0, 1.0]])
+    assert np.array_equal(ds.M, [[1, 1, 0], [1, 1, 0], [0, 0, 1]])
+    assert np.allclose(ds.X[0], [6, 6, 6, 1, 0, 0]) and np.allclose(ds.X[2], [6, 6, 6, 0, 1, 0])
+    base = learn.single_best_baseline(ds, table)
+    # geometric means of (0.5, 1.0) and (1.0, 0.5) tie: the first slot wins
+    assert base[0] == 0 and base[1] == 2
+    assert np.allclose(learn.achieved(ds, [1, 0, 2]), [1.0, 1.0, 1.0])
+    s = learn.summarize(np.array([1.0, 0.5, 1.0, 1.0]))
+    assert s["median"] == 1.0 and s["share_ge_0.95"] == 0.75
+    assert s["geomean"] == pytest.approx(0.5 ** 0.25)
+
+
+def test_model_file_checks_its_table():
+    table = [(0, (1, 2)), (1, (3, 4))]
+    pred = learn.Predictor(table, np.zeros(6), np.ones(6), np.zeros(10, dtype=np.float32))
+    s = pred.to_json()
+    back = learn.Predictor.from_json(s, check_table=table)
+    assert back.table == table
+    with pytest.raises(ValueError):
+        learn.Predictor.from_json(s, check_table=[(0, (9, 9))])
+    bad = json.loads(s)
+    bad["table"][0][1][0] = 77
+    with pytest.raises(ValueError):
+        learn.Predictor.from_json(json.dumps(bad))
+
+
+def test_shipped_database_covers_the_registry():
+    path = os.path.join(os.path.dirname(learn.__file__), "data", "tune_db.json.gz")
+    if not os.path.exists(path):
+        pytest.skip("no shipped database")
+    db = tune.load_compact(path)
+    dts = {r["dtype"] for r in db.records}
+    assert dts == {0, 1}
+    n_shapes = len({(r["dtype"], r["m"], r["n"], r["k"]) for r in db.records})
+    assert n_shapes == 7000
