@@ -40,6 +40,10 @@ PEAK_F64_TFLOPS = 78.6       # MI355X FP64 matrix peak (published)
 PEAK_F32_TFLOPS = 157.3
 PEAK_BF16_TFLOPS = 2516.6
 PEAK_INT8_TOPS = 5033.2
+# Measured HBM traffic of the N = 8192 FP64 launch (FETCH_SIZE x 2.0 + WRITE_SIZE x
+# 1.0, the factors a plain copy of known size gives); valid for the kernel as
+# profiled -- to be re-measured whenever the FP64 tile kernel changes.
+TRAFFIC_F64_N8192 = 14.75e9
 
 
 def parse():
@@ -304,7 +308,10 @@ def main():
         "roofline": {"bound": "mfma", "achieved": round(flops / (kern_ms * 1e-3) / 1e12, 3),
                      "peak": PEAK_F64_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(flops / (kern_ms * 1e-3) / 1e12 / PEAK_F64_TFLOPS, 4),
-                     "traffic": None,
+                     # HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE runs in
+                     # profiles/gemm_tiled_f64_N8192_traffic.md (copy-calibrated)
+                     "traffic": TRAFFIC_F64_N8192 if n == 8192 else None,
+                     "traffic_unit": "bytes per launch",
                      "kernel": "gemm_tiled_kernel<double,256,128,16,4,2,2,1,0,true> "
                                "(one launch per step)",
                      "kernel_avg_ms": round(kern_ms, 4),
