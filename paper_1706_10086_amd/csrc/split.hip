@@ -480,6 +480,132 @@ split_pairs_i8_kernel(PairArgs a) {
     }
 }
 
+// int8, pipelined: one wave per SIMD (4 waves as 2 x 2), each wave a 64 x 32
+// block of C held as two 32x32 accumulators per level (256 accumulator
+// registers).  Three LDS stages are filled by direct global->LDS loads (no
+// staging registers).  While the products of chunk c run, each fragment register
+// is refilled with chunk c+1 right after its last use in chunk c, and chunk c+2
+// is loading into the third stage; one barrier per chunk publishes a stage whose
+// loads were issued a whole chunk earlier.  Slice buffers are addressed with
+// 32-bit offsets (each below 4 GiB, checked on the host).
+constexpr int Q_BM = 128, Q_BN = 64;
+constexpr int Q_UNITS = 16;                              // units of one row run
+constexpr int Q_SROW = 17;                               // padded LDS row (units)
+constexpr int Q_STAGE = (Q_BM + Q_BN) * Q_SROW;          // 3264 units per stage
+constexpr int Q_LOADS = (Q_STAGE + 255) / 256;           // load instructions per wave
+
+__device__ __attribute__((always_inline)) inline void q_issue_loads(
+    const PairArgs &a, uint32_t a_row0, uint32_t b_row0, uint32_t ch, u32x4 *stage, int wave,
+    int lane) {
+    const uint32_t run = 256u, stride = (uint32_t)a.nch * 256u;
+#pragma unroll
+    for (int i = 0; i < Q_LOADS; ++i) {
+        const int first = i * 256 + wave * 64;        // first unit of this wave instruction
+        if (first >= Q_STAGE) continue;               // uniform per wave
+        const int u = first + lane;
+        const uint8_t *src;
+        if (u < Q_BM * Q_SROW) {
+            const int row = u / Q_SROW, c = u % Q_SROW;
+            src = a.QA + ((a_row0 + row) * stride + ch * run + (uint32_t)(c < Q_UNITS ? c : Q_UNITS - 1) * 16u);
+        } else {
+            const int v = u - Q_BM * Q_SROW;
+            const int row = v / Q_SROW, c = v % Q_SROW;
+            src = a.QB + ((b_row0 + row) * stride + ch * run + (uint32_t)(c < Q_UNITS ? c : Q_UNITS - 1) * 16u);
+        }
+        __builtin_amdgcn_global_load_lds(
+            (const void *)src, (__attribute__((address_space(3))) void *)(stage + first), 16, 0, 0);
+    }
+}
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+split_pairs_i8_pipe_kernel(PairArgs a) {
+    __shared__ u32x4 lds[3 * Q_STAGE];
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = wave >> 1, wn = wave & 1;
+    int tm, tn;
+    tile_of_block(blockIdx.x, gridDim.x, a.tiles_m, a.tiles_n, tm, tn);
+    const int64_t m0 = (int64_t)tm * Q_BM, n0 = (int64_t)tn * Q_BN;
+    const int r32 = lane & 31, kh = lane >> 5;
+    const int a_off0 = (wm * 64 + r32) * Q_SROW + kh;            // m-tile 0
+    const int a_off1 = (wm * 64 + 32 + r32) * Q_SROW + kh;       // m-tile 1
+    const int b_off = Q_BM * Q_SROW + (wn * 32 + r32) * Q_SROW + kh;
+
+    v16i acc[8][2];
+#pragma unroll
+    for (int l = 0; l < 8; ++l) {
+        acc[l][0] = v16i{};
+        acc[l][1] = v16i{};
+    }
+    v4i fa[8][2], fb[8];
+
+    const uint32_t ar0 = (uint32_t)m0, br0 = (uint32_t)n0;
+    // products of the current chunk; every fragment is reloaded from the next
+    // stage right after its last use (after the last chunk the reloads read a
+    // stale stage and are never used -- they stay inside the LDS allocation)
+    auto products = [&](const u32x4 *nst) {
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+#pragma unroll
+            for (int t = 7 - s; t >= 0; --t) {
+#pragma unroll
+                for (int mt = 0; mt < 2; ++mt)
+                    acc[s + t][mt] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[s][mt], fb[t],
+                                                                            acc[s + t][mt], 0, 0, 0);
+                // fb[t] is last used by slice s = 7 - t; the scheduling barriers
+                // keep each reload next to the products it overlaps
+                if (t == 7 - s) {
+                    fb[t] = __builtin_bit_cast(v4i, nst[b_off + 2 * t]);
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+            fa[s][0] = __builtin_bit_cast(v4i, nst[a_off0 + 2 * s]);
+            fa[s][1] = __builtin_bit_cast(v4i, nst[a_off1 + 2 * s]);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    };
+
+    const uint32_t c0 = (uint32_t)a.ch0, c1 = (uint32_t)a.ch1;
+    q_issue_loads(a, ar0, br0, c0, lds, wave, lane);
+    if (c0 + 1 < c1) q_issue_loads(a, ar0, br0, c0 + 1, lds + Q_STAGE, wave, lane);
+    __builtin_amdgcn_s_waitcnt(0x0F70);          // vmcnt(0)
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+        fa[s][0] = __builtin_bit_cast(v4i, lds[a_off0 + 2 * s]);
+        fa[s][1] = __builtin_bit_cast(v4i, lds[a_off1 + 2 * s]);
+        fb[s] = __builtin_bit_cast(v4i, lds[b_off + 2 * s]);
+    }
+    int st = 0;                                   // stage of chunk c
+    for (uint32_t c = c0; c < c1; ++c) {
+        // publish chunk c+1 (own loads done, then everyone's)
+        __builtin_amdgcn_s_waitcnt(0x0F70);      // vmcnt(0)
+        __syncthreads();
+        const int st1 = st == 2 ? 0 : st + 1;
+        const int st2 = st1 == 2 ? 0 : st1 + 1;
+        if (c + 2 < c1) q_issue_loads(a, ar0, br0, c + 2, lds + st2 * Q_STAGE, wave, lane);
+        products(lds + st1 * Q_STAGE);
+        st = st1;
+    }
+
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            double hi = (double)acc[0][mt][r] * 0x1p21;
+            hi = hi + (double)acc[1][mt][r] * 0x1p14;
+            hi = hi + (double)acc[2][mt][r] * 0x1p7;
+            hi = hi + (double)acc[3][mt][r];
+            double lo = (double)acc[4][mt][r] * 0x1p21;
+            lo = lo + (double)acc[5][mt][r] * 0x1p14;
+            lo = lo + (double)acc[6][mt][r] * 0x1p7;
+            lo = lo + (double)acc[7][mt][r];
+            const double v = fma(hi, 0x1p-35, lo * 0x1p-63);
+            store_c(a, m0 + wm * 64 + mt * 32 + acc_row(lane, r), n0 + wn * 32 + r32, v);
+        }
+}
+
 // ---------------------------------------------------------------------------
 // Host side: workspace and driver.
 // ---------------------------------------------------------------------------
@@ -522,10 +648,19 @@ static int32_t ws_reserve(Workspace &w, size_t bytes) {
 
 static inline int64_t round_up(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
 
+// A slice-pair kernel and its launch shape.
+struct PairKernel {
+    void (*fn)(PairArgs);
+    int tile_m, tile_n, threads;
+};
+
+constexpr int64_t SPLIT_PAD = 128;   // m and n padded to a multiple of every pair tile
+
 template <typename F>
 static int32_t run_split(const GemmArgs &g, hipStream_t s, Workspace &w, int max_pass_k,
-                         void (*pairs)(PairArgs)) {
-    const int64_t mp = round_up(g.m, PBM), np = round_up(g.n, PBN), kp = round_up(g.k, KPAD);
+                         PairKernel pk) {
+    const int64_t mp = round_up(g.m, SPLIT_PAD), np = round_up(g.n, SPLIT_PAD),
+                  kp = round_up(g.k, KPAD);
     const size_t a_bytes = (size_t)mp * kp * F::S * F::ELEM;
     const size_t b_bytes = (size_t)np * kp * F::S * F::ELEM;
     const size_t e_bytes = round_up(mp * 4, 256), f_bytes = round_up(np * 4, 256);
@@ -577,8 +712,8 @@ static int32_t run_split(const GemmArgs &g, hipStream_t s, Workspace &w, int max
     pa.ldc = g.ldc;
     pa.nch = kp / F::KC;
     pa.alpha = g.alpha;
-    pa.tiles_m = (int)(mp / PBM);
-    pa.tiles_n = (int)(np / PBN);
+    pa.tiles_m = (int)(mp / pk.tile_m);
+    pa.tiles_n = (int)(np / pk.tile_n);
     const int64_t blocks = (int64_t)pa.tiles_m * pa.tiles_n;
     const int64_t pass_ch = max_pass_k / F::KC;
     const int64_t kch = (g.k + F::KC - 1) / F::KC;   // chunks holding data
@@ -586,7 +721,7 @@ static int32_t run_split(const GemmArgs &g, hipStream_t s, Workspace &w, int max
         pa.ch0 = c0;
         pa.ch1 = c0 + pass_ch < kch ? c0 + pass_ch : kch;
         pa.beta = c0 == 0 ? g.beta : 1.0;
-        hipLaunchKernelGGL(pairs, dim3((unsigned)blocks), dim3(512), 0, s, pa);
+        hipLaunchKernelGGL(pk.fn, dim3((unsigned)blocks), dim3(pk.threads), 0, s, pa);
     }
     he = hipGetLastError();
     if (he != hipSuccess) return set_error(MGEMM_ERR_HIP, "split launch: %s", hipGetErrorString(he));
@@ -600,8 +735,17 @@ int32_t split_gemm(const GemmArgs &g, int32_t dtype, hipStream_t s) {
         return set_error(MGEMM_ERR_HIP, "split: no current device");
     Workspace &w = g_ws[dev];
     std::lock_guard<std::mutex> lock(w.mtx);
-    if (dtype == MGEMM_SPLIT_BF16) return run_split<FmtBF16>(g, s, w, 1 << 17, split_pairs_bf16_kernel);
-    if (dtype == MGEMM_SPLIT_INT8) return run_split<FmtI8>(g, s, w, 1 << 14, split_pairs_i8_kernel);
+    if (dtype == MGEMM_SPLIT_BF16)
+        return run_split<FmtBF16>(g, s, w, 1 << 17, PairKernel{split_pairs_bf16_kernel, PBM, PBN, 512});
+    if (dtype == MGEMM_SPLIT_INT8) {
+        // the pipelined kernel addresses each operand's slices with 32-bit offsets
+        const double big = (double)round_up(g.m > g.n ? g.m : g.n, SPLIT_PAD) *
+                           (double)round_up(g.k, KPAD) * FmtI8::S;
+        if (big >= 4294967296.0)
+            return set_error(MGEMM_ERR_NOCONFIG, "split int8: slices of one operand exceed 4 GiB");
+        return run_split<FmtI8>(g, s, w, 1 << 14,
+                                PairKernel{split_pairs_i8_pipe_kernel, Q_BM, Q_BN, 256});
+    }
     return set_error(MGEMM_ERR_NOCONFIG, "split dtype %d is not built", dtype);
 }
 
