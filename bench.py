@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extras", action="store_true", help="only the FP64 headline leg")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--leg", choices=["split", "batched", "tuner"], default=None,
+                    help="run only this extra leg and print its JSON (for profiling runs)")
     return ap.parse_args()
 
 
@@ -226,6 +228,12 @@ def main():
     mg.lib()
     dev = torch.device("cuda:0")
     n = args.n
+    if args.leg:
+        legs = {"split": lambda: leg_split(mg, torch, dev, n),
+                "batched": lambda: leg_batched(mg, torch, dev),
+                "tuner": lambda: leg_tuner(mg)}
+        print(json.dumps({args.leg: legs[args.leg]()}), flush=True)
+        return 0
     log(f"bench: generating N={n} inputs")
     sa, sb, sc = synth.seeds_for(1, int(np.log2(n)))
     A = synth.uniform_pm1((n, n), sa)
