@@ -43,7 +43,7 @@ PEAK_INT8_TOPS = 5033.2
 # Measured HBM traffic of the N = 8192 FP64 launch (FETCH_SIZE x 2.0 + WRITE_SIZE x
 # 1.0, the factors a plain copy of known size gives); valid for the kernel as
 # profiled -- to be re-measured whenever the FP64 tile kernel changes.
-TRAFFIC_F64_N8192 = 14.75e9
+TRAFFIC_F64_N8192 = 14.83e9
 
 
 def parse():
@@ -290,7 +290,7 @@ def main():
 
     cfg_used = None
     for c in mg.configs(mg.F64):
-        if (c.bm, c.bn, c.bk, c.waves) == (256, 128, 16, 8):
+        if (c.bm, c.bn, c.bk, c.waves, c.double_buffer) == (256, 128, 16, 8, 2):
             cfg_used = c.as_dict()
     out = {
         "metric": METRIC,
@@ -317,10 +317,10 @@ def main():
                      "peak": PEAK_F64_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(flops / (kern_ms * 1e-3) / 1e12 / PEAK_F64_TFLOPS, 4),
                      # HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE runs in
-                     # profiles/gemm_tiled_f64_N8192_traffic.md (copy-calibrated)
+                     # profiles/gemm_pipe_f64_N8192_traffic.md (copy-calibrated)
                      "traffic": TRAFFIC_F64_N8192 if n == 8192 else None,
                      "traffic_unit": "bytes per launch",
-                     "kernel": "gemm_tiled_kernel<double,256,128,16,4,2,2,1,0,true> "
+                     "kernel": "gemm_pipe_kernel<double,256,128,16,4,2> "
                                "(one launch per step)",
                      "kernel_avg_ms": round(kern_ms, 4),
                      "work_per_launch": f"2*N^3 = {flops:.4g} FLOP"},

@@ -77,7 +77,11 @@ enum {
  *   elems_per_thread  contiguous elements one thread copies per global->LDS
  *                     load (the paper's element layer).
  *   double_buffer     1: two LDS stages, the next k-step's tiles are loaded while
- *                     the current one is multiplied; 0: one stage.
+ *                     the current one is multiplied; 0: one stage; 2: three
+ *                     stages filled by direct global->LDS loads two k-steps
+ *                     ahead (FP64 only; needs n, lda and ldb even and 16-byte
+ *                     aligned A and B, else the two-stage kernel of the same
+ *                     tile runs, with the same results).
  *   occupancy         wavefronts per SIMD the kernel is compiled to allow (0: the
  *                     compiler's choice, else 1 or 2) -- the GPU counterpart of
  *                     the paper's hardware threads per core (Sec. 3, Tab. 4).
@@ -130,9 +134,10 @@ MGEMM_API int32_t gemm_batched(int64_t count, const int64_t *m, const int64_t *n
                                int32_t dtype);
 
 /* Builds a reusable plan for one batched launch: problems are grouped by tile
- * configuration (cfgs[i], or the library's choice when cfgs is NULL) and row
- * alignment; per group one persistent kernel takes C tiles from an atomic work
- * list; all groups are captured into one HIP graph.  The plan keeps the problem
+ * configuration (cfgs[i]; when cfgs is NULL every problem uses the registered
+ * 64x64x16 four-wave configuration) and row alignment; per group one persistent
+ * kernel takes C tiles from an atomic work list; all groups are captured into one
+ * HIP graph.  The plan keeps the problem
  * descriptors (pointers, sizes, alpha, beta) -- the matrices must stay valid and
  * are read at each execution.  Problems with k == 0 or alpha == 0 are rejected
  * (MGEMM_ERR_PLAN).  stream: the stream executions run on (NULL: null stream).

@@ -31,6 +31,7 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 typedef double v2d __attribute__((ext_vector_type(2)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef float v2f __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4_t __attribute__((ext_vector_type(4)));
 
 // ---------------------------------------------------------------------------
 // Element-type traits: vector types and the 16x16xK MFMA step.
@@ -260,9 +261,36 @@ __device__ __forceinline__ void tile_gemm(const GemmArgs &p, int64_t m0, int64_t
     }
 
     // Epilogue: lane holds column l16 and rows E::out_row(kq, 0..3) of each fragment.
+    // With small wave tiles (at most 8 fragments, registers to spare) interior tiles
+    // issue all C loads of one fragment row before the stores (no per-element
+    // bounds tests between them); otherwise, and on edge tiles, each element is
+    // tested, loaded and stored in turn.
     const T alpha = (T)p.alpha;
     const T beta = (T)p.beta;
     const bool read_c = p.beta != 0.0;
+    if (FM * FN <= 8 && mrem >= BM && nrem >= BN) {
+#pragma unroll
+        for (int i = 0; i < FM; ++i) {
+            T cv[FN][4];
+            if (read_c) {
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        cv[j][r] = C[(m0 + wm * WM + i * 16 + E::out_row(kq, r)) * ldc + n0 +
+                                     wn * WN + j * 16 + l16];
+            }
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    T *c = C + (m0 + wm * WM + i * 16 + E::out_row(kq, r)) * ldc + n0 + wn * WN +
+                           j * 16 + l16;
+                    *c = read_c ? scale_add(alpha, acc[i][j][r], beta, cv[j][r]) : alpha * acc[i][j][r];
+                }
+        }
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -350,6 +378,254 @@ gemm_batched_kernel(const BatchProblem *__restrict__ probs, int nprob, int64_t t
 }
 
 // ---------------------------------------------------------------------------
+// Pipelined single-GEMM kernel: three LDS stages, direct global->LDS loads.
+// ---------------------------------------------------------------------------
+// WGM x WGN waves (4 or 8: one or two per SIMD), each owning a WM x WN block of
+// C as (WM/16) x (WN/16) accumulator fragments.  Each k-step's A and B tiles are
+// copied into LDS by global_load_lds (16 bytes per lane, no staging registers);
+// while the products of k-step c run from registers, every fragment register is
+// refilled with k-step c+1 right after its last use, and k-step c+2 is loading
+// into the third stage, so the one barrier per k-step publishes a stage whose
+// loads were issued a whole k-step earlier.  The k-sum order per element is the
+// same as gemm_tiled_kernel's, so both give bit-identical results.
+//
+// Requirements (checked by the launcher, which otherwise runs the two-stage
+// kernel of the same tile): n, lda and ldb even, A and B 16-byte aligned.  A
+// partial last k-step (k not a multiple of BK) is loaded element-wise and
+// zero-padded after the pipelined loop.  Rows >= m and columns >= n of the edge
+// tiles load clamped (valid) addresses; their products only reach outputs that
+// are not stored.
+template <typename T, int BM, int BN, int BK, int WGM, int WGN>
+struct PipeShape {
+    static constexpr int NT = 64 * WGM * WGN;
+    static constexpr int WM = BM / WGM, WN = BN / WGN;
+    static constexpr int FM = WM / 16, FN = WN / 16;
+    static constexpr int G = BK / 8;                               // 8-deep k groups
+    static constexpr int ROW_A = BK * (int)sizeof(T) / 16;         // 16-byte units per A row
+    static constexpr int AU = ROW_A + 1;                           // padded A row (units)
+    static constexpr int ROW_B = BN * (int)sizeof(T) / 16;         // units per B row
+    static constexpr int BU = ROW_B + (sizeof(T) == 8 ? 4 : 8);    // padded B row (units)
+    static constexpr int A_UNITS = BM * AU;
+    static constexpr int STAGE = A_UNITS + BK * BU;                // units per stage
+    static constexpr int LOADS = (STAGE + NT - 1) / NT;            // load instructions per wave
+    static constexpr int EPU = 16 / (int)sizeof(T);                // elements per unit
+};
+
+template <typename T, int BM, int BN, int BK, int WGM, int WGN>
+__global__ void __launch_bounds__(64 * WGM * WGN)
+    __attribute__((amdgpu_waves_per_eu(WGM * WGN / 4))) gemm_pipe_kernel(GemmArgs p) {
+    typedef PipeShape<T, BM, BN, BK, WGM, WGN> S;
+    typedef Elem<T> E;
+    typedef typename E::vec2 vec2;
+    typedef typename E::acc4 acc4;
+    static_assert(S::WM % 16 == 0 && S::WN % 16 == 0 && BK % 8 == 0, "tile shape");
+    __shared__ u32x4_t lds[3 * S::STAGE];
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = wave / WGN, wn = wave % WGN;
+    const int tiles_m = (int)((p.m + BM - 1) / BM);
+    const int tiles_n = (int)((p.n + BN - 1) / BN);
+    int tm, tn;
+    tile_of_block(blockIdx.x, gridDim.x, tiles_m, tiles_n, tm, tn);
+    const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
+    const T *__restrict__ A = (const T *)p.A;
+    const T *__restrict__ B = (const T *)p.B;
+    const int64_t lda = p.lda, ldb = p.ldb;
+
+    // Per-lane source byte offsets of each load instruction, relative to the
+    // tile's A panel (A + m0*lda) or B panel (B + n0) at k-step 0.  A wave's 64
+    // units of one instruction lie in one region (A_UNITS is a multiple of 64), so
+    // the panel address is wave-uniform and each load takes one offset register.
+    static_assert(S::A_UNITS % 64 == 0, "A region must end on a wave's load");
+    uint32_t src_off[S::LOADS];
+#pragma unroll
+    for (int i = 0; i < S::LOADS; ++i) {
+        const int u = i * S::NT + wave * 64 + lane;
+        int64_t e;
+        if (u < S::A_UNITS) {
+            const int r = u / S::AU, c = u % S::AU;
+            const int64_t row = m0 + r < p.m ? r : p.m - 1 - m0;
+            e = row * lda + (c < S::ROW_A ? c : S::ROW_A - 1) * S::EPU;
+        } else {
+            const int v = u - S::A_UNITS;
+            const int r = v / S::BU, c = v % S::BU;
+            int64_t col = (int64_t)(c < S::ROW_B ? c : S::ROW_B - 1) * S::EPU;
+            if (col > p.n - n0 - S::EPU) col = p.n - n0 - S::EPU;
+            e = (int64_t)(r < BK ? r : BK - 1) * ldb + col;
+        }
+        src_off[i] = (uint32_t)(e * (int64_t)sizeof(T));
+    }
+    const char *Apanel = (const char *)(A + m0 * lda);
+    const char *Bpanel = (const char *)(B + n0);
+    auto issue = [&](int64_t kstep, u32x4_t *stage) {
+        const char *a_src = Apanel + kstep * (BK * (int64_t)sizeof(T));
+        const char *b_src = Bpanel + kstep * (BK * ldb * (int64_t)sizeof(T));
+#pragma unroll
+        for (int i = 0; i < S::LOADS; ++i) {
+            const int first = i * S::NT + wave * 64;
+            // only the last instruction can run past the stage (uniform per wave)
+            if ((i + 1) * S::NT > S::STAGE && first >= S::STAGE) continue;
+            const char *src = (first < S::A_UNITS ? a_src : b_src) + src_off[i];
+            __builtin_amdgcn_global_load_lds((const void *)src,
+                                             (__attribute__((address_space(3))) void *)(stage + first),
+                                             16, 0, 0);
+        }
+    };
+
+    acc4 acc[S::FM][S::FN];
+#pragma unroll
+    for (int i = 0; i < S::FM; ++i)
+#pragma unroll
+        for (int j = 0; j < S::FN; ++j) acc[i][j] = acc4{0, 0, 0, 0};
+
+    const int l16 = lane & 15, kq = lane >> 4;
+    // A fragment (g, i): unit (g*4 + kq) of row wm*WM + i*16 + l16; B fragment
+    // (g, h, j): element (g*8 + 2kq + h, wn*WN + j*16 + l16) of the B region
+    const int a_unit = (wm * S::WM + l16) * S::AU + kq;
+    const int b_elem = S::A_UNITS * S::EPU + (2 * kq) * S::BU * S::EPU + wn * S::WN + l16;
+    vec2 af[S::G][S::FM];
+    T bf[S::G][2][S::FN];
+    auto read_a = [&](const u32x4_t *st, int g, int i) {
+        af[g][i] = __builtin_bit_cast(vec2, st[a_unit + i * 16 * S::AU + g * 4]);
+    };
+    auto read_b = [&](const u32x4_t *st, int g, int h) {
+        const T *stT = (const T *)st;
+#pragma unroll
+        for (int j = 0; j < S::FN; ++j)
+            bf[g][h][j] = stT[b_elem + (g * 8 + h) * S::BU * S::EPU + j * 16];
+    };
+    // products of one k-step; each fragment is refilled from the next stage right
+    // after its last use (past the last k-step the refills read a stale stage and
+    // are never used)
+    auto products = [&](const u32x4_t *nst) {
+#pragma unroll
+        for (int g = 0; g < S::G; ++g) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+#pragma unroll
+                for (int i = 0; i < S::FM; ++i) {
+#pragma unroll
+                    for (int j = 0; j < S::FN; ++j)
+                        acc[i][j] = E::mma(af[g][i][h], bf[g][h][j], acc[i][j]);
+                    if (h == 1) {
+                        read_a(nst, g, i);
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
+                }
+                read_b(nst, g, h);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+    };
+
+    const int64_t nk = p.k / BK;                 // full k-steps
+    const int ktail = (int)(p.k % BK);           // depth of the partial last k-step
+    if (nk > 0) {
+        issue(0, lds);
+        issue(nk > 1 ? 1 : 0, lds + S::STAGE);
+        __builtin_amdgcn_s_waitcnt(0x0F70);      // vmcnt(0)
+        __syncthreads();
+#pragma unroll
+        for (int g = 0; g < S::G; ++g) {
+#pragma unroll
+            for (int i = 0; i < S::FM; ++i) read_a(lds, g, i);
+            read_b(lds, g, 0);
+            read_b(lds, g, 1);
+        }
+        // Past the end the loads repeat the last k-step (in bounds, never used),
+        // which keeps the loop free of branches around the products.
+        int st = 0;
+        for (int64_t c = 0; c < nk; ++c) {
+            __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): own loads of k-step c+1
+            __syncthreads();
+            const int st1 = st == 2 ? 0 : st + 1;
+            const int st2 = st1 == 2 ? 0 : st1 + 1;
+            issue(c + 2 < nk ? c + 2 : nk - 1, lds + st2 * S::STAGE);
+            products(lds + st1 * S::STAGE);
+            st = st1;
+        }
+        __builtin_amdgcn_s_waitcnt(0x0F70);      // no load may land after this point
+    }
+    if (ktail) {
+        // The partial k-step: element-wise loads, zero outside A and B (as the
+        // two-stage kernel pads), into stage 0 once every wave is done with LDS.
+        __syncthreads();
+        const int64_t k0 = nk * BK;
+        T *sT = (T *)lds;
+        for (int e = tid; e < BM * BK; e += S::NT) {
+            const int r = e / BK, c = e % BK;
+            sT[r * S::AU * S::EPU + c] =
+                m0 + r < p.m && c < ktail ? A[(m0 + r) * lda + k0 + c] : (T)0;
+        }
+        for (int e = tid; e < BK * BN; e += S::NT) {
+            const int r = e / BN, c = e % BN;
+            sT[S::A_UNITS * S::EPU + r * S::BU * S::EPU + c] =
+                r < ktail && n0 + c < p.n ? B[(k0 + r) * ldb + n0 + c] : (T)0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int g = 0; g < S::G; ++g) {
+#pragma unroll
+            for (int i = 0; i < S::FM; ++i) read_a(lds, g, i);
+            read_b(lds, g, 0);
+            read_b(lds, g, 1);
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int i = 0; i < S::FM; ++i)
+#pragma unroll
+                    for (int j = 0; j < S::FN; ++j)
+                        acc[i][j] = E::mma(af[g][i][h], bf[g][h][j], acc[i][j]);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+
+    // Epilogue as in tile_gemm: batched C loads for interior tiles.
+    T *__restrict__ C = (T *)p.C;
+    const int64_t ldc = p.ldc, mrem = p.m - m0, nrem = p.n - n0;
+    const T alpha = (T)p.alpha, beta = (T)p.beta;
+    const bool read_c = p.beta != 0.0;
+    if (mrem >= BM && nrem >= BN) {
+#pragma unroll
+        for (int i = 0; i < S::FM; ++i) {
+            T cv[S::FN][4];
+            if (read_c) {
+#pragma unroll
+                for (int j = 0; j < S::FN; ++j)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        cv[j][r] = C[(m0 + wm * S::WM + i * 16 + E::out_row(kq, r)) * ldc + n0 +
+                                     wn * S::WN + j * 16 + l16];
+            }
+#pragma unroll
+            for (int j = 0; j < S::FN; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    T *c = C + (m0 + wm * S::WM + i * 16 + E::out_row(kq, r)) * ldc + n0 +
+                           wn * S::WN + j * 16 + l16;
+                    *c = read_c ? scale_add(alpha, acc[i][j][r], beta, cv[j][r]) : alpha * acc[i][j][r];
+                }
+        }
+        return;
+    }
+#pragma unroll
+    for (int i = 0; i < S::FM; ++i)
+#pragma unroll
+        for (int j = 0; j < S::FN; ++j) {
+            const int64_t col = wn * S::WN + j * 16 + l16;
+            if (col >= nrem) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t row = wm * S::WM + i * 16 + E::out_row(kq, r);
+                if (row >= mrem) continue;
+                T *c = C + (m0 + row) * ldc + n0 + col;
+                *c = read_c ? scale_add(alpha, acc[i][j][r], beta, *c) : alpha * acc[i][j][r];
+            }
+        }
+}
+
+// ---------------------------------------------------------------------------
 // Launchers and registries.
 // ---------------------------------------------------------------------------
 template <typename T, int BM, int BN, int BK, int WGM, int WGN, int EPT, int DBUF, int OCC,
@@ -385,6 +661,36 @@ int batched_occupancy() {
     return nb > 0 ? nb : 1;
 }
 
+// The pipelined kernel where its requirements hold, else the two-stage kernel of
+// the same tile (FWGM x FWGN waves), which sums in the same order.
+template <typename T, int BM, int BN, int BK, int WGM, int WGN, int FWGM, int FWGN>
+hipError_t launch_pipe(const GemmArgs &a, hipStream_t s) {
+    // 32-bit per-lane byte offsets: BM rows of A and BK rows of B must span < 2^31 bytes
+    const bool ok = a.k >= 1 && a.n >= 16 / (int64_t)sizeof(T) &&
+                    a.n % (16 / (int64_t)sizeof(T)) == 0 && a.lda % 2 == 0 && a.ldb % 2 == 0 &&
+                    ((uintptr_t)a.A % 16) == 0 && ((uintptr_t)a.B % 16) == 0 &&
+                    (int64_t)BM * a.lda * (int64_t)sizeof(T) < ((int64_t)1 << 31) &&
+                    ((int64_t)BK * a.ldb + BN) * (int64_t)sizeof(T) < ((int64_t)1 << 31);
+    if (!ok) return launch_tiled<T, BM, BN, BK, FWGM, FWGN, 2, 1, 0, true>(a, s);
+    int64_t blocks = ((a.m + BM - 1) / BM) * ((a.n + BN - 1) / BN);
+    if (blocks <= 0) return hipSuccess;
+    if (blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL((gemm_pipe_kernel<T, BM, BN, BK, WGM, WGN>), dim3((unsigned)blocks),
+                       dim3(64 * WGM * WGN), 0, s, a);
+    return hipGetLastError();
+}
+
+// Registry entry of a pipelined configuration (double_buffer = 2: three stages);
+// unaligned rows and batched plans use the two-stage kernel of the same tile.
+#define MGEMM_PIPE_CFG(T, BM, BN, BK, WGM, WGN, FWGM, FWGN)                            \
+    {{BM, BN, BK, WGM * WGN, 2, 2, WGM * WGN / 4},                                        \
+     &launch_pipe<T, BM, BN, BK, WGM, WGN, FWGM, FWGN>,                                   \
+     &launch_tiled<T, BM, BN, BK, FWGM, FWGN, 2, 1, 0, false>,                            \
+     {&launch_batched<T, BM, BN, BK, FWGM, FWGN, 2, 1, 0, true>,                          \
+      &launch_batched<T, BM, BN, BK, FWGM, FWGN, 2, 1, 0, false>},                        \
+     {&batched_occupancy<T, BM, BN, BK, FWGM, FWGN, 2, 1, 0, true>,                       \
+      &batched_occupancy<T, BM, BN, BK, FWGM, FWGN, 2, 1, 0, false>}}
+
 #define MGEMM_CFG(T, BM, BN, BK, WGM, WGN, EPT, DBUF, OCC)                              \
     {{BM, BN, BK, WGM * WGN, EPT, DBUF, OCC},                                             \
      &launch_tiled<T, BM, BN, BK, WGM, WGN, EPT, DBUF, OCC, true>,                        \
@@ -406,6 +712,11 @@ static const KernelEntry kF64[] = {
     MGEMM_CFG(double, 64, 64, 16, 2, 2, 2, 1, 0),
     MGEMM_CFG(double, 64, 64, 32, 2, 2, 2, 1, 0),
     MGEMM_CFG(double, 32, 32, 16, 1, 1, 2, 1, 0),
+    // three-stage direct-load kernels (one or two waves per SIMD; with one wave per
+    // SIMD, as 128x128 with 4 waves or smaller tiles, they measured slower than the
+    // two-stage kernels of the same tile, so only these two are registered)
+    MGEMM_PIPE_CFG(double, 256, 128, 16, 4, 2, 4, 2),
+    MGEMM_PIPE_CFG(double, 128, 128, 16, 4, 2, 2, 2),
 };
 
 static const KernelEntry kF32[] = {

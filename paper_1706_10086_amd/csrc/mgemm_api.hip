@@ -123,8 +123,8 @@ struct Pref {
 };
 
 static const Pref kPrefF64[] = {
-    {{256, 128, 16, 8, 2, 1, 0}, 512},
-    {{128, 128, 16, 4, 2, 1, 2}, 256},
+    {{256, 128, 16, 8, 2, 2, 2}, 512},
+    {{128, 128, 16, 8, 2, 2, 2}, 256},
     {{128, 64, 32, 4, 4, 0, 2}, 256},
     {{64, 64, 16, 4, 2, 1, 0}, 256},
     {{32, 32, 16, 1, 2, 1, 0}, 0},

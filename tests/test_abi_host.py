@@ -80,7 +80,7 @@ def test_config_registry(L):
         assert len(cs) >= 1
         for c in cs:
             assert c.bm % 16 == 0 and c.bn % 16 == 0 and c.bk % 8 == 0
-            assert c.waves in (1, 2, 4, 8) and c.double_buffer in (0, 1) and c.occupancy in (0, 1, 2)
+            assert c.waves in (1, 2, 4, 8) and c.double_buffer in (0, 1, 2) and c.occupancy in (0, 1, 2)
         assert len({c.as_tuple() for c in cs}) == len(cs)
     assert L.mgemm_config_count(9) < 0
     c = mg.Cfg()

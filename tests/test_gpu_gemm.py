@@ -88,7 +88,9 @@ def test_parity_256_uniform_alpha_beta(dev, orc):
 
 
 SHAPES = [(1, 1, 1), (1, 7, 3), (17, 33, 65), (64, 64, 64), (128, 128, 16), (129, 127, 17),
-          (255, 257, 129), (127, 131, 137), (300, 200, 1000), (16, 1024, 8), (1000, 3, 5)]
+          (255, 257, 129), (127, 131, 137), (300, 200, 1000), (16, 1024, 8), (1000, 3, 5),
+          # even n and k: the shapes the three-stage kernels take, with ragged edges
+          (33, 2, 16), (129, 130, 48), (257, 254, 166), (5, 300, 2)]
 
 
 @pytest.mark.parametrize("dtype", [mg.F64, mg.F32])
@@ -198,6 +200,48 @@ def test_all_configs_uniform_ragged(dev, orc):
         got = run_gemm(dev, A, B, C, 1.5, 0.5, cfg=cfg)
         err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
         assert err <= 1e-13, (cfg, err)
+
+
+def _twin(cfg):
+    """The two-stage configuration a three-stage one falls back to (same tile)."""
+    for c in mg.configs(mg.F64):
+        if (c.bm, c.bn, c.bk, c.double_buffer, c.elems_per_thread, c.occupancy) == \
+                (cfg.bm, cfg.bn, cfg.bk, 1, 2, 0):
+            return c
+    raise AssertionError(f"no two-stage twin for {cfg}")
+
+
+@pytest.mark.parametrize("padded", [False, True])
+def test_three_stage_matches_two_stage_bitwise(dev, orc, padded):
+    """The direct-load three-stage kernels sum in the two-stage kernel's order, so
+    on their own domain (even n and leading dimensions) the results agree bit for
+    bit, including partial last k-steps, ragged edges and padded leading
+    dimensions; both are within 1e-13 of the oracle."""
+    pipes = [c for c in mg.configs(mg.F64) if c.double_buffer == 2]
+    assert pipes
+    for (m, n, k) in [(1, 2, 16), (64, 64, 64), (200, 258, 16), (257, 130, 333),
+                      (300, 2, 1024), (513, 384, 47), (129, 1030, 8)]:
+        A = synth.uniform_pm1((m, k), m + 31)
+        B = synth.uniform_pm1((k, n), n + 37)
+        C = synth.uniform_pm1((m, n), k + 41)
+        ref = orc.gemm_f64(1.5, A, B, 0.5, C)
+        lda, ldb = (k + (2 if k % 2 == 0 else 3), n + 6) if padded else (k, n)
+        Abuf = torch.full((m, lda), float("nan"), device=dev, dtype=torch.float64)
+        Bbuf = torch.full((k, ldb), float("nan"), device=dev, dtype=torch.float64)
+        Abuf[:, :k] = to_dev(A, dev)
+        Bbuf[:, :n] = to_dev(B, dev)
+        for cfg in pipes:
+            say(f"three-stage vs two-stage cfg={cfg} shape={(m, n, k)} padded={padded}")
+            outs = []
+            for c in (cfg, _twin(cfg)):
+                tC = to_dev(C, dev)
+                mg.gemm(Abuf[:, :k], Bbuf[:, :n], tC, 1.5, 0.5, cfg=c)
+                outs.append(tC)
+            torch.cuda.synchronize()
+            assert torch.equal(outs[0], outs[1]), (cfg, m, n, k)
+            got = outs[0].cpu().numpy()
+            err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+            assert err <= 1e-13, (cfg, m, n, k, err)
 
 
 @pytest.mark.parametrize("n", [8192])
