@@ -14,6 +14,9 @@ dimension) and return new arrays; the caller's inputs are never modified.
                     Oishi 2005, Dot2), the high-accuracy reference.
 * ``split_*``    -- the split-precision (Ozaki) emulation: exponents, slices, exact
                     slice-pair products and the full recombined product.
+* ``crt_gemm``   -- the modular-integer emulation (Ozaki scheme II): the exact product
+                    of the operands truncated to ``bits`` bits per row / column, rounded
+                    once; ``crt_bits`` is the operand width the scheme uses for a given k.
 * ``mlp_*``      -- the FP64 MLP cost model (see ``oracle/mlp.py``).
 """
 from __future__ import annotations
@@ -69,6 +72,8 @@ def lib():
         L.orc_split_pair_product.argtypes = [i64, i64, i64, p, p, p]
         L.orc_split_bits.argtypes = [i32, p, p]
         L.orc_split_bits.restype = i32
+        L.orc_crt_gemm.argtypes = [i64, i64, i64, d, p, i64, p, i64, d, p, i64, i32, i32]
+        L.orc_crt_gemm.restype = i32
         L.orc_num_procs.restype = i32
         _lib = L
     return _lib
@@ -198,3 +203,43 @@ def split_pair_product(QA: np.ndarray, QB: np.ndarray) -> np.ndarray:
     G = np.zeros((m, n), dtype=np.int64)
     lib().orc_split_pair_product(m, n, k, _ptr(QA), _ptr(QB), _ptr(G))
     return G
+
+
+# The modular emulation carries the exact product of the truncated operands in
+# residues modulo 16 pairwise coprime moduli whose product exceeds 2^125; the
+# reconstruction is unambiguous while |sum| <= 2^123 (a quarter of that product).
+# Operands of b bits give |sum| < k 2^(2b), hence the widest safe b for a given k:
+CRT_SUM_BITS = 123
+
+
+def crt_bits(k: int) -> int:
+    """Largest b with k * 2^(2b) <= 2^123 (b <= 62)."""
+    if k < 1:
+        raise ValueError("k >= 1")
+    b = 62
+    while k * (1 << (2 * b)) > (1 << CRT_SUM_BITS):
+        b -= 1
+    return b
+
+
+def crt_gemm(alpha, A, B, beta=0.0, C=None, bits: int | None = None,
+             nthreads: int = 1) -> np.ndarray:
+    """Modular-integer emulated FP64 GEMM: exact product of the operands truncated
+    to ``bits`` bits (default ``crt_bits(k)``), rounded once.  Raises
+    FloatingPointError on non-finite input."""
+    A, lda = _mat(A)
+    B, ldb = _mat(B)
+    m, k = A.shape
+    _, n = B.shape
+    if bits is None:
+        bits = crt_bits(max(k, 1))
+    C = np.zeros((m, n)) if C is None else np.array(C, dtype=np.float64, order="C", copy=True)
+    rc = lib().orc_crt_gemm(m, n, k, float(alpha), _ptr(A), lda, _ptr(B), ldb,
+                            float(beta), _ptr(C), max(1, n), int(bits), int(nthreads))
+    if rc == ERR_NONFINITE:
+        raise FloatingPointError("non-finite input")
+    if rc == -14:
+        raise OverflowError("k * 2^(2 bits) too large for the exact sum")
+    if rc != 0:
+        raise ValueError(f"crt_gemm status {rc}")
+    return C

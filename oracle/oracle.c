@@ -367,4 +367,66 @@ int orc_split_gemm(int64_t m, int64_t n, int64_t k, double alpha,
     return ORC_OK;
 }
 
+/* ---------------------------------------------------------------------------
+ * Modular-integer emulation (Ozaki scheme II: Ozaki, Uchino, Imamura 2025).
+ *
+ * The scheme scales each row of A and each column of B by a power of two,
+ * truncates them to integers of at most `bits` bits, and obtains the exact
+ * integer product from its residues modulo several small pairwise coprime
+ * moduli (Chinese remainder theorem).  The moduli only carry the product; what
+ * the scheme computes is fixed by the truncated operands, and that is what this
+ * function writes out directly:
+ *   e_i, f_j  exponents of the row / column maxima (as orc_split_row_exponents),
+ *   A'_ip = trunc(A_ip 2^(bits - e_i)),  B'_pj = trunc(B_pj 2^(bits - f_j)),
+ *   C_ij  = round(sum_p A'_ip B'_pj) 2^(e_i + f_j - 2 bits)   (one rounding),
+ * then alpha*acc + beta*C as in orc_gemm_f64.  |A'|, |B'| < 2^bits, so the exact
+ * sum is below k 2^(2 bits); it is accumulated in 128-bit integers, so the call
+ * is refused (-14) when k 2^(2 bits) > 2^125.  Returns ORC_ERR_NONFINITE (C
+ * untouched) on NaN / Inf in A or B, -13 for bits outside [1, 62].
+ * --------------------------------------------------------------------------- */
+int orc_crt_gemm(int64_t m, int64_t n, int64_t k, double alpha,
+                 const double *A, int64_t lda, const double *B, int64_t ldb,
+                 double beta, double *C, int64_t ldc, int bits, int nthreads)
+{
+    if (m <= 0 || n <= 0) return ORC_OK;
+    if (nthreads < 1) nthreads = 1;
+    if (alpha == 0.0 || k <= 0) {
+        orc_gemm_f64(m, n, 0, alpha, A, lda, B, ldb, beta, C, ldc, 1);
+        return ORC_OK;
+    }
+    if (!all_finite(m, k, A, lda) || !all_finite(k, n, B, ldb)) return ORC_ERR_NONFINITE;
+    if (bits < 1 || bits > 62) return -13;
+    if (log2((double)k) + 2.0 * bits > 125.0) return -14;
+
+    int32_t *e = (int32_t *)malloc(sizeof(int32_t) * (size_t)m);
+    int32_t *f = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int64_t *TA = (int64_t *)malloc(sizeof(int64_t) * (size_t)(m * k));
+    int64_t *TB = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n * k));   /* n x k */
+    orc_split_row_exponents(m, k, A, lda, e);
+    orc_split_col_exponents(k, n, B, ldb, f);
+    for (int64_t i = 0; i < m; ++i)
+        for (int64_t p = 0; p < k; ++p)
+            TA[i * k + p] = (int64_t)trunc(ldexp(A[i * lda + p], bits - e[i]));
+    for (int64_t p = 0; p < k; ++p)
+        for (int64_t j = 0; j < n; ++j)
+            TB[j * k + p] = (int64_t)trunc(ldexp(B[p * ldb + j], bits - f[j]));
+
+#pragma omp parallel for schedule(static) num_threads(nthreads)
+    for (int64_t i = 0; i < m; ++i) {
+        for (int64_t j = 0; j < n; ++j) {
+            __int128 total = 0;
+            for (int64_t p = 0; p < k; ++p)
+                total += (__int128)TA[i * k + p] * (__int128)TB[j * k + p];
+            double acc = ldexp((double)total, e[i] + f[j] - 2 * bits);
+            double *c = C + i * ldc + j;
+            *c = (beta == 0.0) ? alpha * acc : alpha * acc + beta * *c;
+        }
+    }
+    free(TB);
+    free(TA);
+    free(f);
+    free(e);
+    return ORC_OK;
+}
+
 int orc_num_procs(void) { return omp_get_num_procs(); }
