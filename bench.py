@@ -114,7 +114,8 @@ def leg_split(mg, torch, dev, n=8192):
     ref = oracle.gemm_dot2(1.0, A[rows], B, nthreads=oracle.num_procs())
     out = {"n": n, "inputs": "u*2^e, u uniform[-1,1], e uniform integer in [-20,20]",
            "error": f"normwise vs double-double oracle on {len(rows)} sampled rows"}
-    for name, dt in (("f64", mg.F64), ("bf16", mg.SPLIT_BF16), ("int8", mg.SPLIT_INT8)):
+    for name, dt in (("f64", mg.F64), ("bf16", mg.SPLIT_BF16), ("int8", mg.SPLIT_INT8),
+                     ("crt_int8", mg.CRT_INT8)):
         ts = timed(lambda: mg.gemm(tA, tB, tC, 1.0, 0.0, dtype=dt, stream=stream), stream, 5)
         got = tC[torch.from_numpy(rows).to(dev)].cpu().numpy()
         err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
@@ -125,6 +126,11 @@ def leg_split(mg, torch, dev, n=8192):
         log(f"  {name}: {ms:.3f} ms, err {err:.2e}")
     out["bf16"]["mfma_util"] = round(21 * 2.0 * n ** 3 / (out["bf16"]["ms"] * 1e9) / PEAK_BF16_TFLOPS, 4)
     out["int8"]["mfma_util"] = round(36 * 2.0 * n ** 3 / (out["int8"]["ms"] * 1e9) / PEAK_INT8_TOPS, 4)
+    # 16 int8 GEMMs of the zero-padded operands (one per modulus)
+    npad = -(-n // 256) * 256
+    kpad = -(-n // 64) * 64
+    out["crt_int8"]["mfma_util"] = round(16 * 2.0 * npad * npad * kpad /
+                                         (out["crt_int8"]["ms"] * 1e9) / PEAK_INT8_TOPS, 4)
     del tA, tB, tC
     return out
 

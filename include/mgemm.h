@@ -22,7 +22,9 @@
  *          double; the product is emulated from bfloat16 (6 slices, 21 slice
  *          pairs) / int8 (8 slices, 36 pairs) slices of A and B (Ozaki scheme),
  *          see gemm_ex.  MGEMM_SPLIT_FP8 (e4m3 slices) is reserved and returns
- *          MGEMM_ERR_NOCONFIG.
+ *          MGEMM_ERR_NOCONFIG.  MGEMM_CRT_INT8: A, B, C are double; the product
+ *          is emulated from int8 residues of A and B modulo 16 coprime moduli
+ *          (Ozaki scheme II), see gemm_ex.
  * Stream   Work is enqueued on the given HIP stream (NULL: the stream set with
  *          mgemm_set_stream, by default the null stream) and the call returns
  *          after enqueueing.  Launch errors are reported at once; faults surface
@@ -57,7 +59,8 @@ typedef enum {
     MGEMM_F32 = 1,
     MGEMM_SPLIT_BF16 = 2,
     MGEMM_SPLIT_FP8 = 3,
-    MGEMM_SPLIT_INT8 = 4
+    MGEMM_SPLIT_INT8 = 4,
+    MGEMM_CRT_INT8 = 5
 } mgemm_dtype;
 
 enum {
@@ -110,7 +113,17 @@ MGEMM_API int32_t gemm(int64_t m, int64_t n, int64_t k, double alpha,
  * mgemm_release_workspace() or unload.  The call waits once for the scaling
  * step on the stream (to report MGEMM_ERR_NONFINITE before C is touched);
  * split calls on one device are ordered through the shared workspace. cfg must
- * be NULL. */
+ * be NULL.
+ *
+ * MGEMM_CRT_INT8 (modular-integer emulation, Ozaki scheme II): with e_i, f_j the
+ * exponents of the row maxima of A and column maxima of B and b the largest
+ * integer <= 62 with k 2^(2b) <= 2^123, the operands are truncated to integers
+ * A'_ip = trunc(A_ip 2^(b-e_i)), B'_pj = trunc(B_pj 2^(b-f_j)) (|.| < 2^b); the
+ * exact C'_ij = sum_p A'_ip B'_pj is obtained from 16 int8 GEMMs of their
+ * residues modulo 16 pairwise coprime moduli (Chinese remainder theorem), rounded
+ * once to FP64, scaled by 2^(e_i+f_j-2b), and C = alpha*v + beta*C.  k is limited
+ * to 2^40; the workspace (same rules as above) holds about 16*((m+n)*k + m*n)
+ * bytes.  Non-finite input: MGEMM_ERR_NONFINITE, C untouched.  cfg must be NULL. */
 MGEMM_API int32_t gemm_ex(int64_t m, int64_t n, int64_t k, double alpha,
                 const void *A, int64_t lda, const void *B, int64_t ldb,
                 double beta, void *C, int64_t ldc, int32_t dtype,

@@ -20,9 +20,9 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmgemm.so")
 
-F64, F32, SPLIT_BF16, SPLIT_FP8, SPLIT_INT8 = 0, 1, 2, 3, 4
+F64, F32, SPLIT_BF16, SPLIT_FP8, SPLIT_INT8, CRT_INT8 = 0, 1, 2, 3, 4, 5
 DTYPE_NAMES = {F64: "f64", F32: "f32", SPLIT_BF16: "split_bf16", SPLIT_FP8: "split_fp8",
-               SPLIT_INT8: "split_int8"}
+               SPLIT_INT8: "split_int8", CRT_INT8: "crt_int8"}
 SPLIT_SLICES = {SPLIT_BF16: 6, SPLIT_INT8: 8}
 ERR_HIP, ERR_NOMEM, ERR_NONFINITE, ERR_NOCONFIG, ERR_PLAN = 1, 2, 3, 4, 5
 
@@ -180,7 +180,7 @@ def gemm(A, B, C, alpha: float = 1.0, beta: float = 0.0, dtype: int | None = Non
 
     A (m x k), B (k x n), C (m x n) are torch tensors on the current device with
     unit column stride (row stride = leading dimension).  ``dtype`` defaults to
-    the tensors' type; SPLIT_BF16 / SPLIT_FP8 take float64 tensors."""
+    the tensors' type; the emulated dtypes (SPLIT_*, CRT_INT8) take float64 tensors."""
     m, k = A.shape
     k2, n = B.shape
     if k2 != k or tuple(C.shape) != (m, n):

@@ -1,0 +1,465 @@
+// Modular-integer emulation of an FP64 GEMM on int8 matrix cores (Ozaki scheme
+// II: Ozaki, Uchino, Imamura, "Ozaki Scheme II: A GEMM-oriented emulation of
+// floating-point matrix multiplication using an integer modular technique", 2025).
+//
+// C = alpha*A*B + beta*C with FP64 A, B, C:
+//  1. scale     e_i, f_j: exponents of the row / column maxima (shared with the
+//               slice emulation); b = the operand width, the largest b <= 62 with
+//               k 2^(2b) <= 2^123.
+//  2. residues  A'_ip = trunc(A_ip 2^(b - e_i)) and B'_pj = trunc(B_pj 2^(b - f_j))
+//               are integers below 2^b; their residues modulo the 16 moduli below,
+//               in [-p/2, p/2), are stored as int8 planes (B transposed, so both
+//               operands are k-contiguous).
+//  3. products  one int8 GEMM per modulus on the matrix cores with exact int32
+//               accumulation (reduced modulo p every 2^16 k), whose result modulo
+//               p is stored as one byte per element.
+//  4. combine   the Chinese remainder theorem gives the exact integer
+//               C'_ij = sum_p A'_ip B'_pj from its 16 residues (|C'| <= 2^123, a
+//               quarter of the moduli's product), which is rounded once to FP64,
+//               scaled by 2^(e_i + f_j - 2b) and the epilogue alpha*v + beta*C
+//               applied.
+//
+// Against the slice emulation with int8 slices (36 slice-pair products of the
+// same operand width), this needs 16 products of the full width, each a plain
+// int8 GEMM.
+#include <limits.h>
+
+#include "mgemm_internal.h"
+
+namespace mgemm {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+// Pairwise coprime moduli, the largest such set below 2^8: product > 2^125.37.
+static const int kModuli[CRT_MODULI] = {256, 255, 253, 251, 247, 241, 239, 233,
+                                        229, 227, 223, 217, 211, 199, 197, 193};
+__constant__ int kModuliDev[CRT_MODULI] = {256, 255, 253, 251, 247, 241, 239, 233,
+                                           229, 227, 223, 217, 211, 199, 197, 193};
+
+struct CrtResidueArgs {
+    int p[CRT_MODULI];
+    int c32[CRT_MODULI];     // 2^32 mod p
+};
+
+// ---------------------------------------------------------------------------
+// 2. Residues.
+// ---------------------------------------------------------------------------
+// Residues of the integer a (|a| < 2^62, held exactly in a double) modulo each p,
+// as int8 in [-p/2, p/2): a = hi 2^32 + lo with 0 <= lo < 2^32 and |hi| < 2^30.
+__device__ inline void residues_of(double a, const CrtResidueArgs &ra, int8_t (&r)[CRT_MODULI]) {
+    const double hi = floor(a * 0x1p-32);
+    const double lo = a - hi * 0x1p32;
+    const int hi_i = (int)hi;
+    const uint32_t lo_u = (uint32_t)lo;
+#pragma unroll
+    for (int t = 0; t < CRT_MODULI; ++t) {
+        const int p = ra.p[t];
+        int v = ((hi_i % p) * ra.c32[t] + (int)(lo_u % (uint32_t)p)) % p;   // (-p, p)
+        if (v > (p - 1) / 2) v -= p;
+        if (v < -(p / 2)) v += p;
+        r[t] = (int8_t)v;
+    }
+}
+
+// Thread per (row, 16 consecutive k) of A; rows >= m and k >= k give zeros.
+__global__ void __launch_bounds__(256)
+crt_residue_a_kernel(const double *__restrict__ A, int64_t m, int64_t k, int64_t lda,
+                     const int *__restrict__ e, int bits, int8_t *__restrict__ Q, int64_t mp,
+                     int64_t kp, CrtResidueArgs ra) {
+    const int64_t groups = kp / 16;
+    const int64_t total = mp * groups;
+    const int64_t plane = mp * kp;
+    for (int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gid < total;
+         gid += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = gid / groups;
+        const int64_t p0 = (gid - i * groups) * 16;
+        const int ex = i < m ? e[i] : 0;
+        uint32_t w[CRT_MODULI][4];
+#pragma unroll
+        for (int t = 0; t < CRT_MODULI; ++t) w[t][0] = w[t][1] = w[t][2] = w[t][3] = 0;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int64_t p = p0 + v;
+            const double x = (i < m && p < k) ? trunc(ldexp(A[i * lda + p], bits - ex)) : 0.0;
+            int8_t r[CRT_MODULI];
+            residues_of(x, ra, r);
+#pragma unroll
+            for (int t = 0; t < CRT_MODULI; ++t)
+                w[t][v >> 2] |= (uint32_t)(uint8_t)r[t] << (8 * (v & 3));
+        }
+#pragma unroll
+        for (int t = 0; t < CRT_MODULI; ++t)
+            *(u32x4 *)(Q + t * plane + i * kp + p0) = u32x4{w[t][0], w[t][1], w[t][2], w[t][3]};
+    }
+}
+
+// 64 (k) x 64 (n) tile of B through LDS; thread (column j, 16 consecutive k) ->
+// the residues of column j, stored k-contiguous.
+__global__ void __launch_bounds__(256)
+crt_residue_b_kernel(const double *__restrict__ B, int64_t k, int64_t n, int64_t ldb,
+                     const int *__restrict__ fexp, int bits, int8_t *__restrict__ Q, int64_t np,
+                     int64_t kp, CrtResidueArgs ra) {
+    __shared__ double tile[64][65];
+    const int tid = threadIdx.x;
+    const int64_t j0 = (int64_t)blockIdx.x * 64;
+    const int64_t p0 = (int64_t)blockIdx.y * 64;
+    for (int idx = tid; idx < 64 * 64; idx += 256) {
+        const int pr = idx >> 6, jc = idx & 63;
+        const int64_t p = p0 + pr, j = j0 + jc;
+        tile[pr][jc] = (p < k && j < n) ? B[p * ldb + j] : 0.0;
+    }
+    __syncthreads();
+    const int jc = tid >> 2;
+    const int pg = (tid & 3) * 16;
+    const int64_t j = j0 + jc;
+    const int fe = j < n ? fexp[j] : INT_MIN;
+    const int ex = fe == INT_MIN ? 0 : fe;
+    uint32_t w[CRT_MODULI][4];
+#pragma unroll
+    for (int t = 0; t < CRT_MODULI; ++t) w[t][0] = w[t][1] = w[t][2] = w[t][3] = 0;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const double x = trunc(ldexp(tile[pg + v][jc], bits - ex));
+        int8_t r[CRT_MODULI];
+        residues_of(x, ra, r);
+#pragma unroll
+        for (int t = 0; t < CRT_MODULI; ++t)
+            w[t][v >> 2] |= (uint32_t)(uint8_t)r[t] << (8 * (v & 3));
+    }
+    const int64_t plane = np * kp;
+#pragma unroll
+    for (int t = 0; t < CRT_MODULI; ++t)
+        *(u32x4 *)(Q + t * plane + j * kp + p0 + pg) = u32x4{w[t][0], w[t][1], w[t][2], w[t][3]};
+}
+
+// ---------------------------------------------------------------------------
+// 3. One int8 GEMM per modulus.
+// ---------------------------------------------------------------------------
+// Work-group: 8 waves (2 x 4, two per SIMD) own a 256 x 256 tile of C for one
+// modulus; each wave a 128 x 64 block as 4 x 2 accumulators of the 32x32x32 int8
+// MFMA.  A stage holds 64 k of the tile's 256 A rows and 256 B columns (rows of
+// 4 data units of 16 bytes plus one pad unit, so the fragment reads of 16
+// consecutive rows hit distinct banks); four stages are filled by direct
+// global->LDS loads three stages ahead, and every fragment register is refilled
+// from the next stage right after its last use.  Operands are zero-padded to
+// whole tiles and stages, so no load or store needs a bounds test.
+constexpr int G_KS = CRT_KSTEP;                 // k per stage
+constexpr int G_ROW = G_KS / 16 + 1;            // units per LDS row
+constexpr int G_AUNITS = CRT_TILE * G_ROW;      // A part of a stage (units)
+constexpr int G_STAGE = 2 * G_AUNITS;           // units per stage
+constexpr int G_NST = 4;                        // stages
+constexpr int G_THREADS = 512;
+constexpr int G_LOADS = G_STAGE / G_THREADS;    // load instructions per lane per stage
+constexpr int G_PASS = (1 << 16) / G_KS;        // stages between modular reductions
+static_assert(G_STAGE % G_THREADS == 0 && G_AUNITS % 64 == 0, "load split");
+static_assert(G_NST * G_STAGE * 16 <= 163840, "LDS");
+
+struct CrtGemmArgs {
+    const int8_t *QA;
+    const int8_t *QB;
+    uint8_t *R;
+    int64_t plane_a, plane_b, plane_r;
+    int64_t kp, np;
+    int tiles_m, tiles_n, nstages;
+};
+
+// 32x32 accumulator element r of lane l: row 8(r/4) + 4(l/32) + r%4, column l%32.
+__device__ inline int crt_acc_row(int lane, int r) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }
+
+__global__ void __launch_bounds__(G_THREADS) __attribute__((amdgpu_waves_per_eu(2)))
+crt_gemm_kernel(CrtGemmArgs a) {
+    __shared__ u32x4 lds[G_NST * G_STAGE];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = wave >> 2, wn = wave & 3;
+
+    // work-group -> (modulus, tile): the moduli one after another, each walked as
+    // one GEMM's tiles (XCD-aware, grouped rows)
+    const int tiles = a.tiles_m * a.tiles_n;
+    int lid = blockIdx.x;
+    {
+        const int full = (int)(gridDim.x / 8) * 8;
+        if (lid < full) lid = (lid % 8) * (full / 8) + lid / 8;
+    }
+    const int t = lid / tiles;
+    int tm, tn;
+    tile_of_block(lid - t * tiles, 0, a.tiles_m, a.tiles_n, tm, tn);
+    const int p = kModuliDev[t];
+    const int8_t *qa = a.QA + t * a.plane_a + (int64_t)tm * CRT_TILE * a.kp;
+    const int8_t *qb = a.QB + t * a.plane_b + (int64_t)tn * CRT_TILE * a.kp;
+
+    uint32_t off[G_LOADS];
+#pragma unroll
+    for (int i = 0; i < G_LOADS; ++i) {
+        const int u = i * G_THREADS + wave * 64 + lane;
+        const int v = u < G_AUNITS ? u : u - G_AUNITS;
+        const int r = v / G_ROW, c = v % G_ROW;
+        off[i] = (uint32_t)r * (uint32_t)a.kp + (uint32_t)(c < G_ROW - 1 ? c : G_ROW - 2) * 16u;
+    }
+    auto issue = [&](int chunk, int st) {
+        const int8_t *sa = qa + (int64_t)chunk * G_KS;
+        const int8_t *sb = qb + (int64_t)chunk * G_KS;
+#pragma unroll
+        for (int i = 0; i < G_LOADS; ++i) {
+            const int first = i * G_THREADS + wave * 64;          // uniform per wave
+            const int8_t *src = (first < G_AUNITS ? sa : sb) + off[i];
+            __builtin_amdgcn_global_load_lds((const void *)src,
+                                             (__attribute__((address_space(3))) void *)(lds + st * G_STAGE + first),
+                                             16, 0, 0);
+        }
+    };
+
+    v16i acc[4][2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc[i][0] = acc[i][1] = v16i{};
+
+    const int a_unit = (wm * 128 + (lane & 31)) * G_ROW + (lane >> 5);
+    const int b_unit = G_AUNITS + (wn * 64 + (lane & 31)) * G_ROW + (lane >> 5);
+    v4i fa[2][4], fb[2][2];
+    auto read_a = [&](const u32x4 *st, int kk, int mt) {
+        fa[kk][mt] = __builtin_bit_cast(v4i, st[a_unit + mt * 32 * G_ROW + kk * 2]);
+    };
+    auto read_b = [&](const u32x4 *st, int kk, int nt) {
+        fb[kk][nt] = __builtin_bit_cast(v4i, st[b_unit + nt * 32 * G_ROW + kk * 2]);
+    };
+    // products of one stage; each fragment is refilled from the next stage right
+    // after its last use (past the last stage the refills read a stale stage and
+    // are never used)
+    auto products = [&](const u32x4 *nst) {
+#pragma unroll
+        for (int kk = 0; kk < 2; ++kk) {
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) {
+#pragma unroll
+                for (int nt = 0; nt < 2; ++nt)
+                    acc[mt][nt] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[kk][mt], fb[kk][nt],
+                                                                         acc[mt][nt], 0, 0, 0);
+                read_a(nst, kk, mt);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            read_b(nst, kk, 0);
+            read_b(nst, kk, 1);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    };
+
+    const int nst = a.nstages;
+    // chunks 0..2 in flight; wait for chunk 0 (10 = two chunks' loads may remain)
+    issue(0, 0);
+    issue(nst > 1 ? 1 : nst - 1, 1);
+    issue(nst > 2 ? 2 : nst - 1, 2);
+    static_assert(G_LOADS == 5, "the wait counts below assume 5 loads per stage");
+    __builtin_amdgcn_s_waitcnt(0x0F7A);          // vmcnt(10)
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 2; ++kk) {
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) read_a(lds, kk, mt);
+        read_b(lds, kk, 0);
+        read_b(lds, kk, 1);
+    }
+    int st = 0;                                   // stage of chunk c
+    for (int c0 = 0; c0 < nst; c0 += G_PASS) {
+        const int c1 = c0 + G_PASS < nst ? c0 + G_PASS : nst;
+        for (int c = c0; c < c1; ++c) {
+            __builtin_amdgcn_s_waitcnt(0x0F75);  // vmcnt(5): chunk c+1 has landed
+            __syncthreads();
+            const int st1 = (st + 1) & 3;
+            // chunk c+3 into the stage of chunk c-1 (past the end: the last chunk
+            // again, in bounds and never used)
+            issue(c + 3 < nst ? c + 3 : nst - 1, (st + 3) & 3);
+            products(lds + st1 * G_STAGE);
+            st = st1;
+        }
+        if (c1 < nst) {
+            // keep |acc| < 2^31: 2^16 products of at most 2^14 each per pass
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) acc[mt][nt][r] %= p;
+        }
+    }
+    __builtin_amdgcn_s_waitcnt(0x0F70);          // vmcnt(0): no load lands after this point
+
+    uint8_t *R = a.R + t * a.plane_r;
+    const int64_t row0 = (int64_t)tm * CRT_TILE + wm * 128;
+    const int64_t col0 = (int64_t)tn * CRT_TILE + wn * 64 + (lane & 31);
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                int v = acc[mt][nt][r] % p;
+                if (v < 0) v += p;
+                R[(row0 + mt * 32 + crt_acc_row(lane, r)) * a.np + col0 + nt * 32] = (uint8_t)v;
+            }
+}
+
+// ---------------------------------------------------------------------------
+// 4. Chinese-remainder reconstruction, one rounding, epilogue.
+// ---------------------------------------------------------------------------
+// With P the moduli's product, M_t = P / p_t and W_t = M_t (M_t^-1 mod p_t) < P,
+// S = sum_t r_t W_t is congruent to C' modulo P; q = round(S / P) is found from
+// sum_t r_t (W_t / P) in FP64 (|C'| <= P/4 keeps S/P within 1/4 of q, far above
+// the estimate's error), and C' = S - q P is computed modulo 2^128, which is exact
+// because |C'| < 2^127.
+struct CrtReconArgs {
+    uint64_t w_lo[CRT_MODULI], w_hi[CRT_MODULI];
+    double wf[CRT_MODULI];
+    uint64_t p_lo, p_hi;
+};
+
+// Signed 128-bit integer (hi, lo) -> FP64, rounded to nearest even.
+__device__ inline double i128_to_double(uint64_t hi, uint64_t lo) {
+    const bool neg = (int64_t)hi < 0;
+    if (neg) {
+        lo = ~lo + 1;
+        hi = ~hi + (lo == 0 ? 1 : 0);
+    }
+    double v;
+    if (hi == 0) {
+        v = (double)lo;                            // one rounding of an exact sum
+    } else {
+        const int lz = __clzll((long long)hi);     // 0..63
+        const int drop = 64 - lz;                  // bits below the top 64
+        const uint64_t top = lz == 0 ? hi : (hi << lz) | (lo >> drop);
+        const uint64_t rest = lz == 0 ? lo : lo << lz;
+        // a nonzero remainder below the top 64 bits turns an exact half into
+        // "above half"; it cannot change any other rounding decision
+        v = ldexp((double)(top | (rest != 0 ? 1 : 0)), drop);
+    }
+    return neg ? -v : v;
+}
+
+__global__ void __launch_bounds__(256)
+crt_reconstruct_kernel(const uint8_t *__restrict__ R, int64_t plane_r, int64_t np,
+                       const int *__restrict__ e, const int *__restrict__ fexp, int two_bits,
+                       double *__restrict__ C, int64_t m, int64_t n, int64_t ldc, double alpha,
+                       double beta, CrtReconArgs rc) {
+    const int64_t total = m * n;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = idx / n, j = idx - i * n;
+        const uint8_t *rp = R + i * np + j;
+        unsigned __int128 s = 0;
+        double qf = 0.0;
+#pragma unroll
+        for (int t = 0; t < CRT_MODULI; ++t) {
+            const uint32_t r = rp[t * plane_r];
+            s += (unsigned __int128)r * (((unsigned __int128)rc.w_hi[t] << 64) | rc.w_lo[t]);
+            qf = fma((double)r, rc.wf[t], qf);
+        }
+        const uint64_t q = (uint64_t)rint(qf);
+        s -= (unsigned __int128)q * (((unsigned __int128)rc.p_hi << 64) | rc.p_lo);
+        const double v = i128_to_double((uint64_t)(s >> 64), (uint64_t)s);
+        const int fe = fexp[j];
+        const double val = ldexp(v, e[i] + (fe == INT_MIN ? 0 : fe) - two_bits);
+        double *c = C + i * ldc + j;
+        if (beta == 0.0) {
+            *c = alpha * val;
+        } else {
+#pragma clang fp contract(off)
+            *c = alpha * val + beta * *c;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host side.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct CrtTables {
+    CrtResidueArgs ra;
+    CrtReconArgs rc;
+    CrtTables() {
+        typedef unsigned __int128 u128;
+        u128 P = 1;
+        for (int t = 0; t < CRT_MODULI; ++t) P *= (u128)kModuli[t];
+        for (int t = 0; t < CRT_MODULI; ++t) {
+            const int p = kModuli[t];
+            ra.p[t] = p;
+            ra.c32[t] = (int)(((uint64_t)1 << 32) % (uint64_t)p);
+            const u128 M = P / (u128)p;
+            // inverse of M mod p by the extended Euclidean algorithm
+            long long r0 = (long long)(M % (u128)p), r1 = p, s0 = 1, s1 = 0;
+            while (r1 != 0) {
+                const long long qq = r0 / r1;
+                long long tmp = r0 - qq * r1; r0 = r1; r1 = tmp;
+                tmp = s0 - qq * s1; s0 = s1; s1 = tmp;
+            }
+            const long long inv = ((s0 % p) + p) % p;       // r0 == 1: coprime moduli
+            const u128 W = M * (u128)inv;                    // < P: inv < p
+            rc.w_lo[t] = (uint64_t)W;
+            rc.w_hi[t] = (uint64_t)(W >> 64);
+            rc.wf[t] = (double)W / (double)P;
+        }
+        rc.p_lo = (uint64_t)P;
+        rc.p_hi = (uint64_t)(P >> 64);
+    }
+};
+
+const CrtTables &tables() {
+    static const CrtTables tb;
+    return tb;
+}
+
+}  // namespace
+
+// The operand width b: the largest b <= 62 with k 2^(2b) <= 2^123, i.e.
+// k <= 2^(123 - 2b) (at least 1).
+int crt_operand_bits(int64_t k) {
+    int b = 62;
+    for (; b > 1; --b) {
+        const int sh = 123 - 2 * b;
+        if (sh >= 0 && (sh >= 63 || k <= ((int64_t)1 << sh))) break;
+    }
+    return b;
+}
+
+hipError_t crt_launch(const GemmArgs &g, hipStream_t s, const int *e, const int *fexp, int bits,
+                      int8_t *QA, int8_t *QB, uint8_t *R, int64_t mp, int64_t np, int64_t kp) {
+    const CrtTables &tb = tables();
+    {
+        const int64_t groups = mp * (kp / 16);
+        int64_t blocks = (groups + 255) / 256;
+        if (blocks > 1 << 20) blocks = 1 << 20;
+        hipLaunchKernelGGL(crt_residue_a_kernel, dim3((unsigned)blocks), dim3(256), 0, s,
+                           (const double *)g.A, g.m, g.k, g.lda, e, bits, QA, mp, kp, tb.ra);
+        hipLaunchKernelGGL(crt_residue_b_kernel, dim3((unsigned)(np / 64), (unsigned)(kp / 64)),
+                           dim3(256), 0, s, (const double *)g.B, g.k, g.n, g.ldb, fexp, bits, QB,
+                           np, kp, tb.ra);
+    }
+    {
+        CrtGemmArgs ga;
+        ga.QA = QA;
+        ga.QB = QB;
+        ga.R = R;
+        ga.plane_a = mp * kp;
+        ga.plane_b = np * kp;
+        ga.plane_r = mp * np;
+        ga.kp = kp;
+        ga.np = np;
+        ga.tiles_m = (int)(mp / CRT_TILE);
+        ga.tiles_n = (int)(np / CRT_TILE);
+        ga.nstages = (int)(kp / CRT_KSTEP);
+        const int64_t blocks = (int64_t)ga.tiles_m * ga.tiles_n * CRT_MODULI;
+        hipLaunchKernelGGL(crt_gemm_kernel, dim3((unsigned)blocks), dim3(G_THREADS), 0, s, ga);
+    }
+    {
+        const int64_t total = g.m * g.n;
+        int64_t blocks = (total + 255) / 256;
+        if (blocks > 1 << 20) blocks = 1 << 20;
+        hipLaunchKernelGGL(crt_reconstruct_kernel, dim3((unsigned)blocks), dim3(256), 0, s,
+                           (const uint8_t *)R, mp * np, np, e, fexp, 2 * bits, (double *)g.C, g.m,
+                           g.n, g.ldc, g.alpha, g.beta, tb.rc);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace mgemm

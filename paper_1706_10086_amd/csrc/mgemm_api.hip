@@ -61,7 +61,7 @@ int32_t check_args(int64_t m, int64_t n, int64_t k, double alpha, const void *A,
     if (ldb < (n > 1 ? n : 1)) return set_error(-8, "ldb < max(1,n)");
     if (m > 0 && n > 0 && C == nullptr) return set_error(-10, "C is NULL");
     if (ldc < (n > 1 ? n : 1)) return set_error(-11, "ldc < max(1,n)");
-    if (dtype < MGEMM_F64 || dtype > MGEMM_SPLIT_INT8) return set_error(-12, "unknown dtype %d", dtype);
+    if (dtype < MGEMM_F64 || dtype > MGEMM_CRT_INT8) return set_error(-12, "unknown dtype %d", dtype);
     if (reads_ab) {
         const size_t es = elem_size(dtype);
         const size_t cb = span_bytes(m, n, ldc, es);
@@ -236,14 +236,14 @@ int32_t mgemm_set_stream(void *stream) {
 const char *mgemm_last_error(void) { return g_err.c_str(); }
 
 int32_t mgemm_config_count(int32_t dtype) {
-    if (dtype < MGEMM_F64 || dtype > MGEMM_SPLIT_INT8) return -1;
+    if (dtype < MGEMM_F64 || dtype > MGEMM_CRT_INT8) return -1;
     int cnt = 0;
     registry(dtype, &cnt);
     return cnt;
 }
 
 int32_t mgemm_config_get(int32_t dtype, int32_t i, mgemm_cfg *out) {
-    if (dtype < MGEMM_F64 || dtype > MGEMM_SPLIT_INT8) return -1;
+    if (dtype < MGEMM_F64 || dtype > MGEMM_CRT_INT8) return -1;
     int cnt = 0;
     const KernelEntry *reg = registry(dtype, &cnt);
     if (i < 0 || i >= cnt) return -2;

@@ -74,6 +74,19 @@ __device__ inline void tile_of_block(int bid, int nblocks, int tiles_m, int tile
     tn = in_group / gm;
 }
 
+// Modular-integer (Ozaki scheme II) emulation: operands are padded to whole
+// CRT_TILE x CRT_KSTEP blocks; crt_launch runs the residue, product and
+// reconstruction kernels on exponents already computed (e per row of A, fexp per
+// column of B, INT_MIN for an all-zero column).  Workspace: QA and QB hold
+// CRT_MODULI int8 planes of mp x kp and np x kp, R CRT_MODULI byte planes of
+// mp x np.
+constexpr int CRT_MODULI = 16;
+constexpr int CRT_TILE = 256;
+constexpr int CRT_KSTEP = 64;
+int crt_operand_bits(int64_t k);
+hipError_t crt_launch(const GemmArgs &g, hipStream_t s, const int *e, const int *fexp, int bits,
+                      int8_t *QA, int8_t *QB, uint8_t *R, int64_t mp, int64_t np, int64_t kp);
+
 // Number of work-groups a configuration launches for an m x n output.
 inline int64_t tiles_of(int64_t m, int64_t n, const mgemm_cfg &c) {
     return ((m + c.bm - 1) / c.bm) * ((n + c.bn - 1) / c.bn);

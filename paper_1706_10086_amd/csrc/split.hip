@@ -729,6 +729,51 @@ static int32_t run_split(const GemmArgs &g, hipStream_t s, Workspace &w, int max
     return 0;
 }
 
+// Modular-integer emulation: the scale step above, then the residue, product and
+// reconstruction kernels of crt.hip on the same workspace.
+static int32_t run_crt(const GemmArgs &g, hipStream_t s, Workspace &w) {
+    if (g.k > ((int64_t)1 << 40))
+        return set_error(MGEMM_ERR_NOCONFIG, "crt int8: k above 2^40");
+    const int64_t mp = round_up(g.m, CRT_TILE), np = round_up(g.n, CRT_TILE),
+                  kp = round_up(g.k, CRT_KSTEP);
+    // the product kernel addresses a tile's rows of one plane with 32-bit offsets
+    if ((double)CRT_TILE * (double)kp >= 4294967296.0)
+        return set_error(MGEMM_ERR_NOCONFIG, "crt int8: k too large for one plane");
+    const size_t qa_bytes = (size_t)CRT_MODULI * mp * kp, qb_bytes = (size_t)CRT_MODULI * np * kp;
+    const size_t r_bytes = (size_t)CRT_MODULI * mp * np;
+    const size_t e_bytes = round_up(mp * 4, 256), f_bytes = round_up(np * 4, 256);
+    int32_t rc = ws_reserve(w, e_bytes + f_bytes + 256 + qa_bytes + qb_bytes + r_bytes);
+    if (rc) return rc;
+    int *e = (int *)w.base;
+    int *fexp = (int *)(w.base + e_bytes);
+    int *flag = (int *)(w.base + e_bytes + f_bytes);
+    int8_t *QA = (int8_t *)(w.base + e_bytes + f_bytes + 256);
+    int8_t *QB = QA + qa_bytes;
+    uint8_t *R = (uint8_t *)(QB + qb_bytes);
+
+    hipError_t he = hipStreamWaitEvent(s, w.done, 0);
+    if (he != hipSuccess) return set_error(MGEMM_ERR_HIP, "crt: %s", hipGetErrorString(he));
+    hipLaunchKernelGGL(split_init_kernel, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s,
+                       fexp, np, flag);
+    hipLaunchKernelGGL(split_row_scale_kernel, dim3((unsigned)(g.m < 65536 ? g.m : 65536)),
+                       dim3(256), 0, s, (const double *)g.A, g.m, g.k, g.lda, e, flag);
+    {
+        int64_t gy = (g.k + COL_ROWS - 1) / COL_ROWS;
+        if (gy > 65535) gy = 65535;
+        hipLaunchKernelGGL(split_col_scale_kernel, dim3((unsigned)((g.n + 255) / 256), (unsigned)gy),
+                           dim3(256), 0, s, (const double *)g.B, g.k, g.n, g.ldb, fexp, flag);
+    }
+    he = hipMemcpyAsync(w.host_flag, flag, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (he == hipSuccess) he = hipStreamSynchronize(s);
+    if (he != hipSuccess) return set_error(MGEMM_ERR_HIP, "crt scale: %s", hipGetErrorString(he));
+    if (*w.host_flag) return set_error(MGEMM_ERR_NONFINITE, "crt: A or B holds NaN or Inf");
+
+    he = crt_launch(g, s, e, fexp, crt_operand_bits(g.k), QA, QB, R, mp, np, kp);
+    if (he != hipSuccess) return set_error(MGEMM_ERR_HIP, "crt launch: %s", hipGetErrorString(he));
+    hipEventRecord(w.done, s);
+    return 0;
+}
+
 int32_t split_gemm(const GemmArgs &g, int32_t dtype, hipStream_t s) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES)
@@ -746,6 +791,7 @@ int32_t split_gemm(const GemmArgs &g, int32_t dtype, hipStream_t s) {
         return run_split<FmtI8>(g, s, w, 1 << 14,
                                 PairKernel{split_pairs_i8_pipe_kernel, Q_BM, Q_BN, 256});
     }
+    if (dtype == MGEMM_CRT_INT8) return run_crt(g, s, w);
     return set_error(MGEMM_ERR_NOCONFIG, "split dtype %d is not built", dtype);
 }
 
