@@ -11,8 +11,9 @@
 //               in [-p/2, p/2), are stored as int8 planes (B transposed, so both
 //               operands are k-contiguous).
 //  3. products  one int8 GEMM per modulus on the matrix cores with exact int32
-//               accumulation (reduced modulo p every 2^16 k), whose result modulo
-//               p is stored as one byte per element.
+//               accumulation (in launches of at most 2^16 k, each adding its
+//               residues to the previous ones), whose result modulo p is stored as
+//               one byte per element.
 //  4. combine   the Chinese remainder theorem gives the exact integer
 //               C'_ij = sum_p A'_ip B'_pj from its 16 residues (|C'| <= 2^123, a
 //               quarter of the moduli's product), which is rounded once to FP64,
@@ -23,6 +24,7 @@
 // same operand width), this needs 16 products of the full width, each a plain
 // int8 GEMM.
 #include <limits.h>
+#include <stdlib.h>
 
 #include "mgemm_internal.h"
 
@@ -33,65 +35,71 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 // Pairwise coprime moduli, the largest such set below 2^8: product > 2^125.37.
-static const int kModuli[CRT_MODULI] = {256, 255, 253, 251, 247, 241, 239, 233,
-                                        229, 227, 223, 217, 211, 199, 197, 193};
-__constant__ int kModuliDev[CRT_MODULI] = {256, 255, 253, 251, 247, 241, 239, 233,
-                                           229, 227, 223, 217, 211, 199, 197, 193};
 
-struct CrtResidueArgs {
-    int p[CRT_MODULI];
-    int c32[CRT_MODULI];     // 2^32 mod p
-};
+// The moduli as compile-time constants for the device (t is unrolled), so the
+// residues use constant-divisor arithmetic.
+__host__ __device__ constexpr int modulus(int t) {
+    return t == 0 ? 256 : t == 1 ? 255 : t == 2 ? 253 : t == 3 ? 251 : t == 4 ? 247 :
+           t == 5 ? 241 : t == 6 ? 239 : t == 7 ? 233 : t == 8 ? 229 : t == 9 ? 227 :
+           t == 10 ? 223 : t == 11 ? 217 : t == 12 ? 211 : t == 13 ? 199 : t == 14 ? 197 : 193;
+}
+__host__ __device__ constexpr int pow32_mod(int t) {
+    return (int)(((uint64_t)1 << 32) % (uint64_t)modulus(t));
+}
+__constant__ int kModuliDev[CRT_MODULI] = {modulus(0),  modulus(1),  modulus(2),  modulus(3),
+                                           modulus(4),  modulus(5),  modulus(6),  modulus(7),
+                                           modulus(8),  modulus(9),  modulus(10), modulus(11),
+                                           modulus(12), modulus(13), modulus(14), modulus(15)};
 
 // ---------------------------------------------------------------------------
 // 2. Residues.
 // ---------------------------------------------------------------------------
 // Residues of the integer a (|a| < 2^62, held exactly in a double) modulo each p,
 // as int8 in [-p/2, p/2): a = hi 2^32 + lo with 0 <= lo < 2^32 and |hi| < 2^30.
-__device__ inline void residues_of(double a, const CrtResidueArgs &ra, int8_t (&r)[CRT_MODULI]) {
+__device__ inline void residues_of(double a, int8_t (&r)[CRT_MODULI]) {
     const double hi = floor(a * 0x1p-32);
     const double lo = a - hi * 0x1p32;
     const int hi_i = (int)hi;
     const uint32_t lo_u = (uint32_t)lo;
 #pragma unroll
     for (int t = 0; t < CRT_MODULI; ++t) {
-        const int p = ra.p[t];
-        int v = ((hi_i % p) * ra.c32[t] + (int)(lo_u % (uint32_t)p)) % p;   // (-p, p)
+        const int p = modulus(t);
+        int v = ((hi_i % p) * pow32_mod(t) + (int)(lo_u % (uint32_t)p)) % p;   // (-p, p)
         if (v > (p - 1) / 2) v -= p;
         if (v < -(p / 2)) v += p;
         r[t] = (int8_t)v;
     }
 }
 
-// Thread per (row, 16 consecutive k) of A; rows >= m and k >= k give zeros.
+// Thread per (row, 8 consecutive k) of A; rows >= m and k >= k give zeros.
 __global__ void __launch_bounds__(256)
 crt_residue_a_kernel(const double *__restrict__ A, int64_t m, int64_t k, int64_t lda,
                      const int *__restrict__ e, int bits, int8_t *__restrict__ Q, int64_t mp,
-                     int64_t kp, CrtResidueArgs ra) {
-    const int64_t groups = kp / 16;
+                     int64_t kp) {
+    const int64_t groups = kp / 8;
     const int64_t total = mp * groups;
     const int64_t plane = mp * kp;
     for (int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gid < total;
          gid += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = gid / groups;
-        const int64_t p0 = (gid - i * groups) * 16;
+        const int64_t p0 = (gid - i * groups) * 8;
         const int ex = i < m ? e[i] : 0;
-        uint32_t w[CRT_MODULI][4];
+        uint32_t w[CRT_MODULI][2];
 #pragma unroll
-        for (int t = 0; t < CRT_MODULI; ++t) w[t][0] = w[t][1] = w[t][2] = w[t][3] = 0;
+        for (int t = 0; t < CRT_MODULI; ++t) w[t][0] = w[t][1] = 0;
 #pragma unroll
-        for (int v = 0; v < 16; ++v) {
+        for (int v = 0; v < 8; ++v) {
             const int64_t p = p0 + v;
             const double x = (i < m && p < k) ? trunc(ldexp(A[i * lda + p], bits - ex)) : 0.0;
             int8_t r[CRT_MODULI];
-            residues_of(x, ra, r);
+            residues_of(x, r);
 #pragma unroll
             for (int t = 0; t < CRT_MODULI; ++t)
                 w[t][v >> 2] |= (uint32_t)(uint8_t)r[t] << (8 * (v & 3));
         }
 #pragma unroll
         for (int t = 0; t < CRT_MODULI; ++t)
-            *(u32x4 *)(Q + t * plane + i * kp + p0) = u32x4{w[t][0], w[t][1], w[t][2], w[t][3]};
+            *(uint2 *)(Q + t * plane + i * kp + p0) = make_uint2(w[t][0], w[t][1]);
     }
 }
 
@@ -100,7 +108,7 @@ crt_residue_a_kernel(const double *__restrict__ A, int64_t m, int64_t k, int64_t
 __global__ void __launch_bounds__(256)
 crt_residue_b_kernel(const double *__restrict__ B, int64_t k, int64_t n, int64_t ldb,
                      const int *__restrict__ fexp, int bits, int8_t *__restrict__ Q, int64_t np,
-                     int64_t kp, CrtResidueArgs ra) {
+                     int64_t kp) {
     __shared__ double tile[64][65];
     const int tid = threadIdx.x;
     const int64_t j0 = (int64_t)blockIdx.x * 64;
@@ -123,7 +131,7 @@ crt_residue_b_kernel(const double *__restrict__ B, int64_t k, int64_t n, int64_t
     for (int v = 0; v < 16; ++v) {
         const double x = trunc(ldexp(tile[pg + v][jc], bits - ex));
         int8_t r[CRT_MODULI];
-        residues_of(x, ra, r);
+        residues_of(x, r);
 #pragma unroll
         for (int t = 0; t < CRT_MODULI; ++t)
             w[t][v >> 2] |= (uint32_t)(uint8_t)r[t] << (8 * (v & 3));
@@ -137,8 +145,8 @@ crt_residue_b_kernel(const double *__restrict__ B, int64_t k, int64_t n, int64_t
 // ---------------------------------------------------------------------------
 // 3. One int8 GEMM per modulus.
 // ---------------------------------------------------------------------------
-// Work-group: 8 waves (2 x 4, two per SIMD) own a 256 x 256 tile of C for one
-// modulus; each wave a 128 x 64 block as 4 x 2 accumulators of the 32x32x32 int8
+// Work-group: WGM x WGN waves own a 256 x 256 tile of C for one modulus; each
+// wave a (256/WGM) x (256/WGN) block as 32x32 accumulators of the 32x32x32 int8
 // MFMA.  A stage holds 64 k of the tile's 256 A rows and 256 B columns (rows of
 // 4 data units of 16 bytes plus one pad unit, so the fragment reads of 16
 // consecutive rows hit distinct banks); four stages are filled by direct
@@ -150,11 +158,12 @@ constexpr int G_ROW = G_KS / 16 + 1;            // units per LDS row
 constexpr int G_AUNITS = CRT_TILE * G_ROW;      // A part of a stage (units)
 constexpr int G_STAGE = 2 * G_AUNITS;           // units per stage
 constexpr int G_NST = 4;                        // stages
-constexpr int G_THREADS = 512;
-constexpr int G_LOADS = G_STAGE / G_THREADS;    // load instructions per lane per stage
-constexpr int G_PASS = (1 << 16) / G_KS;        // stages between modular reductions
-static_assert(G_STAGE % G_THREADS == 0 && G_AUNITS % 64 == 0, "load split");
+constexpr int G_PASS = (1 << 16) / G_KS;        // stages per launch: |acc| < 2^16 * 2^14
+static_assert(G_AUNITS % 64 == 0, "a wave's loads lie in one operand");
 static_assert(G_NST * G_STAGE * 16 <= 163840, "LDS");
+
+// s_waitcnt immediate: vmcnt(n), no wait on the other counters
+constexpr int vmcnt_imm(int n) { return (n & 15) | ((n >> 4) << 14) | 0x70 | 0xF00; }
 
 struct CrtGemmArgs {
     const int8_t *QA;
@@ -162,18 +171,26 @@ struct CrtGemmArgs {
     uint8_t *R;
     int64_t plane_a, plane_b, plane_r;
     int64_t kp, np;
-    int tiles_m, tiles_n, nstages;
+    int tiles_m, tiles_n;
+    int ch0, ch1;          // stages [ch0, ch1) of this pass (at most 2^16 k)
+    int accumulate;        // add the previous passes' residues already in R
 };
 
 // 32x32 accumulator element r of lane l: row 8(r/4) + 4(l/32) + r%4, column l%32.
 __device__ inline int crt_acc_row(int lane, int r) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }
 
-__global__ void __launch_bounds__(G_THREADS) __attribute__((amdgpu_waves_per_eu(2)))
+template <int WGM, int WGN>
+__global__ void __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(WGM * WGN / 4)))
 crt_gemm_kernel(CrtGemmArgs a) {
+    constexpr int NT = 64 * WGM * WGN;
+    constexpr int WTM = CRT_TILE / WGM, WTN = CRT_TILE / WGN;   // wave block
+    constexpr int FM = WTM / 32, FN = WTN / 32;                 // accumulators per wave
+    constexpr int LOADS = G_STAGE / NT;                         // loads per lane per stage
+    static_assert(G_STAGE % NT == 0, "load split");
     __shared__ u32x4 lds[G_NST * G_STAGE];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int wm = wave >> 2, wn = wave & 3;
+    const int wm = wave / WGN, wn = wave % WGN;
 
     // work-group -> (modulus, tile): the moduli one after another, each walked as
     // one GEMM's tiles (XCD-aware, grouped rows)
@@ -190,10 +207,10 @@ crt_gemm_kernel(CrtGemmArgs a) {
     const int8_t *qa = a.QA + t * a.plane_a + (int64_t)tm * CRT_TILE * a.kp;
     const int8_t *qb = a.QB + t * a.plane_b + (int64_t)tn * CRT_TILE * a.kp;
 
-    uint32_t off[G_LOADS];
+    uint32_t off[LOADS];
 #pragma unroll
-    for (int i = 0; i < G_LOADS; ++i) {
-        const int u = i * G_THREADS + wave * 64 + lane;
+    for (int i = 0; i < LOADS; ++i) {
+        const int u = i * NT + wave * 64 + lane;
         const int v = u < G_AUNITS ? u : u - G_AUNITS;
         const int r = v / G_ROW, c = v % G_ROW;
         off[i] = (uint32_t)r * (uint32_t)a.kp + (uint32_t)(c < G_ROW - 1 ? c : G_ROW - 2) * 16u;
@@ -202,8 +219,8 @@ crt_gemm_kernel(CrtGemmArgs a) {
         const int8_t *sa = qa + (int64_t)chunk * G_KS;
         const int8_t *sb = qb + (int64_t)chunk * G_KS;
 #pragma unroll
-        for (int i = 0; i < G_LOADS; ++i) {
-            const int first = i * G_THREADS + wave * 64;          // uniform per wave
+        for (int i = 0; i < LOADS; ++i) {
+            const int first = i * NT + wave * 64;                 // uniform per wave
             const int8_t *src = (first < G_AUNITS ? sa : sb) + off[i];
             __builtin_amdgcn_global_load_lds((const void *)src,
                                              (__attribute__((address_space(3))) void *)(lds + st * G_STAGE + first),
@@ -211,13 +228,15 @@ crt_gemm_kernel(CrtGemmArgs a) {
         }
     };
 
-    v16i acc[4][2];
+    v16i acc[FM][FN];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) acc[i][0] = acc[i][1] = v16i{};
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) acc[i][j] = v16i{};
 
-    const int a_unit = (wm * 128 + (lane & 31)) * G_ROW + (lane >> 5);
-    const int b_unit = G_AUNITS + (wn * 64 + (lane & 31)) * G_ROW + (lane >> 5);
-    v4i fa[2][4], fb[2][2];
+    const int a_unit = (wm * WTM + (lane & 31)) * G_ROW + (lane >> 5);
+    const int b_unit = G_AUNITS + (wn * WTN + (lane & 31)) * G_ROW + (lane >> 5);
+    v4i fa[2][FM], fb[2][FN];
     auto read_a = [&](const u32x4 *st, int kk, int mt) {
         fa[kk][mt] = __builtin_bit_cast(v4i, st[a_unit + mt * 32 * G_ROW + kk * 2]);
     };
@@ -231,72 +250,65 @@ crt_gemm_kernel(CrtGemmArgs a) {
 #pragma unroll
         for (int kk = 0; kk < 2; ++kk) {
 #pragma unroll
-            for (int mt = 0; mt < 4; ++mt) {
+            for (int mt = 0; mt < FM; ++mt) {
 #pragma unroll
-                for (int nt = 0; nt < 2; ++nt)
+                for (int nt = 0; nt < FN; ++nt)
                     acc[mt][nt] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[kk][mt], fb[kk][nt],
                                                                          acc[mt][nt], 0, 0, 0);
                 read_a(nst, kk, mt);
                 __builtin_amdgcn_sched_barrier(0);
             }
-            read_b(nst, kk, 0);
-            read_b(nst, kk, 1);
+#pragma unroll
+            for (int nt = 0; nt < FN; ++nt) read_b(nst, kk, nt);
             __builtin_amdgcn_sched_barrier(0);
         }
     };
 
-    const int nst = a.nstages;
-    // chunks 0..2 in flight; wait for chunk 0 (10 = two chunks' loads may remain)
+    // stages of this pass, counted from its first; chunks 0..2 in flight, wait for
+    // chunk 0 (two chunks' loads may remain)
+    qa += (int64_t)a.ch0 * G_KS;
+    qb += (int64_t)a.ch0 * G_KS;
+    const int nst = a.ch1 - a.ch0;
     issue(0, 0);
     issue(nst > 1 ? 1 : nst - 1, 1);
     issue(nst > 2 ? 2 : nst - 1, 2);
-    static_assert(G_LOADS == 5, "the wait counts below assume 5 loads per stage");
-    __builtin_amdgcn_s_waitcnt(0x0F7A);          // vmcnt(10)
+    __builtin_amdgcn_s_waitcnt(vmcnt_imm(2 * LOADS));
     __syncthreads();
 #pragma unroll
     for (int kk = 0; kk < 2; ++kk) {
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt) read_a(lds, kk, mt);
-        read_b(lds, kk, 0);
-        read_b(lds, kk, 1);
+        for (int mt = 0; mt < FM; ++mt) read_a(lds, kk, mt);
+#pragma unroll
+        for (int nt = 0; nt < FN; ++nt) read_b(lds, kk, nt);
     }
     int st = 0;                                   // stage of chunk c
-    for (int c0 = 0; c0 < nst; c0 += G_PASS) {
-        const int c1 = c0 + G_PASS < nst ? c0 + G_PASS : nst;
-        for (int c = c0; c < c1; ++c) {
-            __builtin_amdgcn_s_waitcnt(0x0F75);  // vmcnt(5): chunk c+1 has landed
-            __syncthreads();
-            const int st1 = (st + 1) & 3;
-            // chunk c+3 into the stage of chunk c-1 (past the end: the last chunk
-            // again, in bounds and never used)
-            issue(c + 3 < nst ? c + 3 : nst - 1, (st + 3) & 3);
-            products(lds + st1 * G_STAGE);
-            st = st1;
-        }
-        if (c1 < nst) {
-            // keep |acc| < 2^31: 2^16 products of at most 2^14 each per pass
-#pragma unroll
-            for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-                for (int nt = 0; nt < 2; ++nt)
-#pragma unroll
-                    for (int r = 0; r < 16; ++r) acc[mt][nt][r] %= p;
-        }
+    for (int c = 0; c < nst; ++c) {
+        __builtin_amdgcn_s_waitcnt(vmcnt_imm(LOADS));   // chunk c+1 has landed
+        __syncthreads();
+        const int st1 = (st + 1) & 3;
+        // chunk c+3 into the stage of chunk c-1 (past the end: the last chunk
+        // again, in bounds and never used)
+        issue(c + 3 < nst ? c + 3 : nst - 1, (st + 3) & 3);
+        products(lds + st1 * G_STAGE);
+        st = st1;
     }
-    __builtin_amdgcn_s_waitcnt(0x0F70);          // vmcnt(0): no load lands after this point
+    __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));       // no load lands after this point
 
     uint8_t *R = a.R + t * a.plane_r;
-    const int64_t row0 = (int64_t)tm * CRT_TILE + wm * 128;
-    const int64_t col0 = (int64_t)tn * CRT_TILE + wn * 64 + (lane & 31);
+    const int64_t row0 = (int64_t)tm * CRT_TILE + wm * WTM;
+    const int64_t col0 = (int64_t)tn * CRT_TILE + wn * WTN + (lane & 31);
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt)
+    for (int mt = 0; mt < FM; ++mt)
 #pragma unroll
-        for (int nt = 0; nt < 2; ++nt)
+        for (int nt = 0; nt < FN; ++nt)
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
+                uint8_t *dst = R + (row0 + mt * 32 + crt_acc_row(lane, r)) * a.np + col0 + nt * 32;
                 int v = acc[mt][nt][r] % p;
+                if (a.accumulate) v += *dst;
+                v %= p;
                 if (v < 0) v += p;
-                R[(row0 + mt * 32 + crt_acc_row(lane, r)) * a.np + col0 + nt * 32] = (uint8_t)v;
+                *dst = (uint8_t)v;
             }
 }
 
@@ -309,9 +321,9 @@ crt_gemm_kernel(CrtGemmArgs a) {
 // the estimate's error), and C' = S - q P is computed modulo 2^128, which is exact
 // because |C'| < 2^127.
 struct CrtReconArgs {
-    uint64_t w_lo[CRT_MODULI], w_hi[CRT_MODULI];
-    double wf[CRT_MODULI];
-    uint64_t p_lo, p_hi;
+    uint32_t w[CRT_MODULI][4];      // W_t as four 32-bit limbs, least significant first
+    double wf[CRT_MODULI];          // W_t / P
+    uint32_t pl[4];                 // P as four 32-bit limbs
 };
 
 // Signed 128-bit integer (hi, lo) -> FP64, rounded to nearest even.
@@ -336,35 +348,62 @@ __device__ inline double i128_to_double(uint64_t hi, uint64_t lo) {
     return neg ? -v : v;
 }
 
+// C' of one element from its 16 residues r_t (byte v of each word rr[t]).
+__device__ inline double crt_value(const uint64_t (&rr)[CRT_MODULI], int v, const CrtReconArgs &rc) {
+    // S = sum_t r_t W_t by 32-bit limbs: each limb sum < 16 * 255 * 2^32 < 2^44
+    uint64_t s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+    double qf = 0.0;
+#pragma unroll
+    for (int t = 0; t < CRT_MODULI; ++t) {
+        const uint32_t r = (uint32_t)(rr[t] >> (8 * v)) & 0xFFu;
+        s0 += (uint64_t)r * rc.w[t][0];
+        s1 += (uint64_t)r * rc.w[t][1];
+        s2 += (uint64_t)r * rc.w[t][2];
+        s3 += (uint64_t)r * rc.w[t][3];
+        qf = fma((double)r, rc.wf[t], qf);
+    }
+    const uint32_t q = (uint32_t)rint(qf);         // < 16 * 256
+    // subtract q P limb by limb (q P_l < 2^44); carries propagate as signed values,
+    // everything modulo 2^128
+    int64_t d0 = (int64_t)s0 - (int64_t)((uint64_t)q * rc.pl[0]);
+    int64_t d1 = (int64_t)s1 - (int64_t)((uint64_t)q * rc.pl[1]) + (d0 >> 32);
+    int64_t d2 = (int64_t)s2 - (int64_t)((uint64_t)q * rc.pl[2]) + (d1 >> 32);
+    int64_t d3 = (int64_t)s3 - (int64_t)((uint64_t)q * rc.pl[3]) + (d2 >> 32);
+    const uint64_t lo = ((uint64_t)(uint32_t)d1 << 32) | (uint32_t)d0;
+    const uint64_t hi = ((uint64_t)(uint32_t)d3 << 32) | (uint32_t)d2;
+    return i128_to_double(hi, lo);
+}
+
+// Thread per 8 consecutive elements of a row of C: one 8-byte load per modulus.
 __global__ void __launch_bounds__(256)
 crt_reconstruct_kernel(const uint8_t *__restrict__ R, int64_t plane_r, int64_t np,
                        const int *__restrict__ e, const int *__restrict__ fexp, int two_bits,
                        double *__restrict__ C, int64_t m, int64_t n, int64_t ldc, double alpha,
                        double beta, CrtReconArgs rc) {
-    const int64_t total = m * n;
+    const int64_t n8 = (n + 7) / 8;
+    const int64_t total = m * n8;
     for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
          idx += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = idx / n, j = idx - i * n;
-        const uint8_t *rp = R + i * np + j;
-        unsigned __int128 s = 0;
-        double qf = 0.0;
+        const int64_t i = idx / n8, j0 = (idx - i * n8) * 8;
+        uint64_t rr[CRT_MODULI];
 #pragma unroll
-        for (int t = 0; t < CRT_MODULI; ++t) {
-            const uint32_t r = rp[t * plane_r];
-            s += (unsigned __int128)r * (((unsigned __int128)rc.w_hi[t] << 64) | rc.w_lo[t]);
-            qf = fma((double)r, rc.wf[t], qf);
-        }
-        const uint64_t q = (uint64_t)rint(qf);
-        s -= (unsigned __int128)q * (((unsigned __int128)rc.p_hi << 64) | rc.p_lo);
-        const double v = i128_to_double((uint64_t)(s >> 64), (uint64_t)s);
-        const int fe = fexp[j];
-        const double val = ldexp(v, e[i] + (fe == INT_MIN ? 0 : fe) - two_bits);
-        double *c = C + i * ldc + j;
-        if (beta == 0.0) {
-            *c = alpha * val;
-        } else {
+        for (int t = 0; t < CRT_MODULI; ++t)
+            rr[t] = *(const uint64_t *)(R + t * plane_r + i * np + j0);
+        const int ei = e[i];
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+            const int64_t j = j0 + v;
+            if (j >= n) break;
+            const double cv = crt_value(rr, v, rc);
+            const int fe = fexp[j];
+            const double val = ldexp(cv, ei + (fe == INT_MIN ? 0 : fe) - two_bits);
+            double *c = C + i * ldc + j;
+            if (beta == 0.0) {
+                *c = alpha * val;
+            } else {
 #pragma clang fp contract(off)
-            *c = alpha * val + beta * *c;
+                *c = alpha * val + beta * *c;
+            }
         }
     }
 }
@@ -375,16 +414,13 @@ crt_reconstruct_kernel(const uint8_t *__restrict__ R, int64_t plane_r, int64_t n
 namespace {
 
 struct CrtTables {
-    CrtResidueArgs ra;
     CrtReconArgs rc;
     CrtTables() {
         typedef unsigned __int128 u128;
         u128 P = 1;
-        for (int t = 0; t < CRT_MODULI; ++t) P *= (u128)kModuli[t];
+        for (int t = 0; t < CRT_MODULI; ++t) P *= (u128)modulus(t);
         for (int t = 0; t < CRT_MODULI; ++t) {
-            const int p = kModuli[t];
-            ra.p[t] = p;
-            ra.c32[t] = (int)(((uint64_t)1 << 32) % (uint64_t)p);
+            const int p = modulus(t);
             const u128 M = P / (u128)p;
             // inverse of M mod p by the extended Euclidean algorithm
             long long r0 = (long long)(M % (u128)p), r1 = p, s0 = 1, s1 = 0;
@@ -395,12 +431,10 @@ struct CrtTables {
             }
             const long long inv = ((s0 % p) + p) % p;       // r0 == 1: coprime moduli
             const u128 W = M * (u128)inv;                    // < P: inv < p
-            rc.w_lo[t] = (uint64_t)W;
-            rc.w_hi[t] = (uint64_t)(W >> 64);
+            for (int l = 0; l < 4; ++l) rc.w[t][l] = (uint32_t)(W >> (32 * l));
             rc.wf[t] = (double)W / (double)P;
         }
-        rc.p_lo = (uint64_t)P;
-        rc.p_hi = (uint64_t)(P >> 64);
+        for (int l = 0; l < 4; ++l) rc.pl[l] = (uint32_t)(P >> (32 * l));
     }
 };
 
@@ -426,14 +460,14 @@ hipError_t crt_launch(const GemmArgs &g, hipStream_t s, const int *e, const int 
                       int8_t *QA, int8_t *QB, uint8_t *R, int64_t mp, int64_t np, int64_t kp) {
     const CrtTables &tb = tables();
     {
-        const int64_t groups = mp * (kp / 16);
+        const int64_t groups = mp * (kp / 8);
         int64_t blocks = (groups + 255) / 256;
         if (blocks > 1 << 20) blocks = 1 << 20;
         hipLaunchKernelGGL(crt_residue_a_kernel, dim3((unsigned)blocks), dim3(256), 0, s,
-                           (const double *)g.A, g.m, g.k, g.lda, e, bits, QA, mp, kp, tb.ra);
+                           (const double *)g.A, g.m, g.k, g.lda, e, bits, QA, mp, kp);
         hipLaunchKernelGGL(crt_residue_b_kernel, dim3((unsigned)(np / 64), (unsigned)(kp / 64)),
                            dim3(256), 0, s, (const double *)g.B, g.k, g.n, g.ldb, fexp, bits, QB,
-                           np, kp, tb.ra);
+                           np, kp);
     }
     {
         CrtGemmArgs ga;
@@ -447,12 +481,23 @@ hipError_t crt_launch(const GemmArgs &g, hipStream_t s, const int *e, const int 
         ga.np = np;
         ga.tiles_m = (int)(mp / CRT_TILE);
         ga.tiles_n = (int)(np / CRT_TILE);
-        ga.nstages = (int)(kp / CRT_KSTEP);
+        const int64_t nstages = kp / CRT_KSTEP;
         const int64_t blocks = (int64_t)ga.tiles_m * ga.tiles_n * CRT_MODULI;
-        hipLaunchKernelGGL(crt_gemm_kernel, dim3((unsigned)blocks), dim3(G_THREADS), 0, s, ga);
+        static const int waves = getenv("MGEMM_CRT_WAVES") ? atoi(getenv("MGEMM_CRT_WAVES")) : 4;
+        // passes of at most 2^16 k keep the int32 sums exact; later passes add
+        // their residues to the stored ones
+        for (int64_t c0 = 0; c0 < nstages; c0 += G_PASS) {
+            ga.ch0 = (int)c0;
+            ga.ch1 = (int)(c0 + G_PASS < nstages ? c0 + G_PASS : nstages);
+            ga.accumulate = c0 > 0;
+            if (waves == 8)
+                hipLaunchKernelGGL((crt_gemm_kernel<2, 4>), dim3((unsigned)blocks), dim3(512), 0, s, ga);
+            else
+                hipLaunchKernelGGL((crt_gemm_kernel<2, 2>), dim3((unsigned)blocks), dim3(256), 0, s, ga);
+        }
     }
     {
-        const int64_t total = g.m * g.n;
+        const int64_t total = g.m * ((g.n + 7) / 8);
         int64_t blocks = (total + 255) / 256;
         if (blocks > 1 << 20) blocks = 1 << 20;
         hipLaunchKernelGGL(crt_reconstruct_kernel, dim3((unsigned)blocks), dim3(256), 0, s,

@@ -404,7 +404,9 @@ struct PipeShape {
     static constexpr int ROW_A = BK * (int)sizeof(T) / 16;         // 16-byte units per A row
     static constexpr int AU = ROW_A + 1;                           // padded A row (units)
     static constexpr int ROW_B = BN * (int)sizeof(T) / 16;         // units per B row
-    static constexpr int BU = ROW_B + (sizeof(T) == 8 ? 4 : 8);    // padded B row (units)
+    // padded B row: stride BN + 8 elements, so the two k rows (2 kq apart) one
+    // fragment read touches fall in distinct banks
+    static constexpr int BU = ROW_B + (sizeof(T) == 8 ? 4 : 2);
     static constexpr int A_UNITS = BM * AU;
     static constexpr int STAGE = A_UNITS + BK * BU;                // units per stage
     static constexpr int LOADS = (STAGE + NT - 1) / NT;            // load instructions per wave
@@ -480,14 +482,14 @@ __global__ void __launch_bounds__(64 * WGM * WGN)
         for (int j = 0; j < S::FN; ++j) acc[i][j] = acc4{0, 0, 0, 0};
 
     const int l16 = lane & 15, kq = lane >> 4;
-    // A fragment (g, i): unit (g*4 + kq) of row wm*WM + i*16 + l16; B fragment
+    // A fragment (g, i): elements g*8 + 2kq, +1 of row wm*WM + i*16 + l16; B fragment
     // (g, h, j): element (g*8 + 2kq + h, wn*WN + j*16 + l16) of the B region
-    const int a_unit = (wm * S::WM + l16) * S::AU + kq;
+    const int a_elem = (wm * S::WM + l16) * S::AU * S::EPU + 2 * kq;
     const int b_elem = S::A_UNITS * S::EPU + (2 * kq) * S::BU * S::EPU + wn * S::WN + l16;
     vec2 af[S::G][S::FM];
     T bf[S::G][2][S::FN];
     auto read_a = [&](const u32x4_t *st, int g, int i) {
-        af[g][i] = __builtin_bit_cast(vec2, st[a_unit + i * 16 * S::AU + g * 4]);
+        af[g][i] = *(const vec2 *)((const T *)st + a_elem + i * 16 * S::AU * S::EPU + g * 8);
     };
     auto read_b = [&](const u32x4_t *st, int g, int h) {
         const T *stT = (const T *)st;
@@ -663,15 +665,17 @@ int batched_occupancy() {
 
 // The pipelined kernel where its requirements hold, else the two-stage kernel of
 // the same tile (FWGM x FWGN waves), which sums in the same order.
-template <typename T, int BM, int BN, int BK, int WGM, int WGN, int FWGM, int FWGN>
+template <typename T, int BM, int BN, int BK, int WGM, int WGN, int FWGM, int FWGN, int FEPT>
 hipError_t launch_pipe(const GemmArgs &a, hipStream_t s) {
-    // 32-bit per-lane byte offsets: BM rows of A and BK rows of B must span < 2^31 bytes
-    const bool ok = a.k >= 1 && a.n >= 16 / (int64_t)sizeof(T) &&
-                    a.n % (16 / (int64_t)sizeof(T)) == 0 && a.lda % 2 == 0 && a.ldb % 2 == 0 &&
+    // 16-byte rows of A and B; 32-bit per-lane byte offsets: BM rows of A and BK
+    // rows of B must span < 2^31 bytes
+    constexpr int64_t EPU = 16 / (int64_t)sizeof(T);
+    const bool ok = a.k >= 1 && a.n >= EPU && a.n % EPU == 0 && a.lda % EPU == 0 &&
+                    a.ldb % EPU == 0 &&
                     ((uintptr_t)a.A % 16) == 0 && ((uintptr_t)a.B % 16) == 0 &&
                     (int64_t)BM * a.lda * (int64_t)sizeof(T) < ((int64_t)1 << 31) &&
                     ((int64_t)BK * a.ldb + BN) * (int64_t)sizeof(T) < ((int64_t)1 << 31);
-    if (!ok) return launch_tiled<T, BM, BN, BK, FWGM, FWGN, 2, 1, 0, true>(a, s);
+    if (!ok) return launch_tiled<T, BM, BN, BK, FWGM, FWGN, FEPT, 1, 0, true>(a, s);
     int64_t blocks = ((a.m + BM - 1) / BM) * ((a.n + BN - 1) / BN);
     if (blocks <= 0) return hipSuccess;
     if (blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
@@ -682,14 +686,16 @@ hipError_t launch_pipe(const GemmArgs &a, hipStream_t s) {
 
 // Registry entry of a pipelined configuration (double_buffer = 2: three stages);
 // unaligned rows and batched plans use the two-stage kernel of the same tile.
-#define MGEMM_PIPE_CFG(T, BM, BN, BK, WGM, WGN, FWGM, FWGN)                            \
-    {{BM, BN, BK, WGM * WGN, 2, 2, WGM * WGN / 4},                                        \
-     &launch_pipe<T, BM, BN, BK, WGM, WGN, FWGM, FWGN>,                                   \
-     &launch_tiled<T, BM, BN, BK, FWGM, FWGN, 2, 1, 0, false>,                            \
-     {&launch_batched<T, BM, BN, BK, FWGM, FWGN, 2, 1, 0, true>,                          \
-      &launch_batched<T, BM, BN, BK, FWGM, FWGN, 2, 1, 0, false>},                        \
-     {&batched_occupancy<T, BM, BN, BK, FWGM, FWGN, 2, 1, 0, true>,                       \
-      &batched_occupancy<T, BM, BN, BK, FWGM, FWGN, 2, 1, 0, false>}}
+// Its elems_per_thread is the elements of one 16-byte direct load; FWGM, FWGN and
+// FEPT name the two-stage fallback (registered on its own as well).
+#define MGEMM_PIPE_CFG(T, BM, BN, BK, WGM, WGN, FWGM, FWGN, FEPT)                      \
+    {{BM, BN, BK, WGM * WGN, 16 / (int)sizeof(T), 2, WGM * WGN / 4},                      \
+     &launch_pipe<T, BM, BN, BK, WGM, WGN, FWGM, FWGN, FEPT>,                             \
+     &launch_tiled<T, BM, BN, BK, FWGM, FWGN, FEPT, 1, 0, false>,                         \
+     {&launch_batched<T, BM, BN, BK, FWGM, FWGN, FEPT, 1, 0, true>,                       \
+      &launch_batched<T, BM, BN, BK, FWGM, FWGN, FEPT, 1, 0, false>},                     \
+     {&batched_occupancy<T, BM, BN, BK, FWGM, FWGN, FEPT, 1, 0, true>,                    \
+      &batched_occupancy<T, BM, BN, BK, FWGM, FWGN, FEPT, 1, 0, false>}}
 
 #define MGEMM_CFG(T, BM, BN, BK, WGM, WGN, EPT, DBUF, OCC)                              \
     {{BM, BN, BK, WGM * WGN, EPT, DBUF, OCC},                                             \
@@ -715,8 +721,8 @@ static const KernelEntry kF64[] = {
     // three-stage direct-load kernels (one or two waves per SIMD; with one wave per
     // SIMD, as 128x128 with 4 waves or smaller tiles, they measured slower than the
     // two-stage kernels of the same tile, so only these two are registered)
-    MGEMM_PIPE_CFG(double, 256, 128, 16, 4, 2, 4, 2),
-    MGEMM_PIPE_CFG(double, 128, 128, 16, 4, 2, 2, 2),
+    MGEMM_PIPE_CFG(double, 256, 128, 16, 4, 2, 4, 2, 2),
+    MGEMM_PIPE_CFG(double, 128, 128, 16, 4, 2, 2, 2, 2),
 };
 
 static const KernelEntry kF32[] = {
@@ -728,6 +734,8 @@ static const KernelEntry kF32[] = {
     MGEMM_CFG(float, 128, 64, 32, 2, 2, 4, 1, 0),
     MGEMM_CFG(float, 64, 64, 16, 2, 2, 2, 1, 0),
     MGEMM_CFG(float, 32, 32, 16, 1, 1, 2, 1, 0),
+    MGEMM_PIPE_CFG(float, 256, 128, 32, 4, 2, 4, 2, 4),
+    MGEMM_PIPE_CFG(float, 128, 128, 32, 4, 2, 2, 2, 4),
 };
 
 const KernelEntry *f64_registry(int *count) {

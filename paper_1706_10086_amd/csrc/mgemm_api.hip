@@ -131,8 +131,8 @@ static const Pref kPrefF64[] = {
 };
 
 static const Pref kPrefF32[] = {
-    {{256, 128, 32, 8, 4, 1, 0}, 512},
-    {{128, 128, 32, 4, 4, 1, 0}, 256},
+    {{256, 128, 32, 8, 4, 2, 2}, 512},
+    {{128, 128, 32, 8, 4, 2, 2}, 256},
     {{128, 64, 32, 4, 4, 1, 0}, 256},
     {{64, 64, 16, 4, 2, 1, 0}, 256},
     {{32, 32, 16, 1, 2, 1, 0}, 0},

@@ -48,6 +48,11 @@ P = 1 << 20   # a fake, never dereferenced device address
     ((4, 4, 4, 1.0, P, 4, P * 4, 4, 0.0, 0, 4, 0), -10),
     ((4, 5, 4, 1.0, P, 4, P * 4, 5, 0.0, P * 2, 4, 0), -11),
     ((4, 4, 4, 1.0, P, 4, P * 4, 4, 0.0, P * 2, 4, 7), -12),
+    ((4, 4, 4, 1.0, P, 4, P * 4, 4, 0.0, P * 2, 4, 6), -12),
+    # every emulated dtype is accepted: the bad leading dimension is reported
+    ((4, 4, 8, 1.0, P, 7, P, 4, 0.0, P * 2, 4, 2), -6),
+    ((4, 4, 8, 1.0, P, 7, P, 4, 0.0, P * 2, 4, 4), -6),
+    ((4, 4, 8, 1.0, P, 7, P, 4, 0.0, P * 2, 4, 5), -6),
     ((4, 4, 4, 1.0, P, 4, P * 4, 4, 0.0, P * 2, 4, -1), -12),
     # C overlapping A
     ((4, 4, 4, 1.0, P, 4, P * 4, 4, 0.0, P + 64, 4, 0), -10),

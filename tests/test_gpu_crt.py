@@ -3,9 +3,10 @@ the C ABI.
 
 The GPU path recovers the exact product of the truncated operands from its
 residues and rounds once, which is exactly the oracle's definition, so results
-are compared BITWISE with the oracle on the same inputs (including k beyond the
-in-kernel modular reduction period of 2^16).  Accuracy against the double-double
-oracle: normwise relative error <= 1e-14 on the wide-range stress inputs."""
+are compared BITWISE with the oracle on the same inputs (including k beyond
+2^16, where the products run in passes whose residues are added modulo p).
+Accuracy against the double-double oracle: normwise relative error <= 1e-14 on
+the wide-range stress inputs."""
 import numpy as np
 import pytest
 
@@ -16,7 +17,6 @@ pytestmark = pytest.mark.gpu
 
 import paper_1706_10086_amd as mg  # noqa: E402
 
-P = 1 << 12
 
 
 def say(*a):
@@ -94,8 +94,8 @@ def test_integer_inputs_exact(dev):
 
 
 def test_k_beyond_reduction_period(dev, orc):
-    """k = 70000 > 2^16: the int32 accumulators are reduced modulo p inside the
-    product kernel; the result is still exact."""
+    """k = 70000 > 2^16: the product runs in two passes (int32 sums stay exact),
+    the second adding its residues to the first's modulo p; the result is exact."""
     m, n, k = 40, 72, 70000
     say(f"crt long k {(m, n, k)}")
     A = synth.wide_range((m, k), 31)
