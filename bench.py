@@ -55,7 +55,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extras", action="store_true", help="only the FP64 headline leg")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--leg", choices=["split", "batched", "tuner"], default=None,
+    ap.add_argument("--leg", choices=["sweep", "split", "batched", "tuner"], default=None,
                     help="run only this extra leg and print its JSON (for profiling runs)")
     return ap.parse_args()
 
@@ -132,6 +132,33 @@ def leg_split(mg, torch, dev, n=8192):
     out["crt_int8"]["mfma_util"] = round(16 * 2.0 * npad * npad * kpad /
                                          (out["crt_int8"]["ms"] * 1e9) / PEAK_INT8_TOPS, 4)
     del tA, tB, tC
+    return out
+
+
+def leg_sweep(mg, torch, dev, sizes=(1024, 2048, 4096, 8192, 16384)):
+    """The square sweep: FP64 and FP32 with the library's default configuration,
+    uniform[-1,1) inputs drawn on the device, alpha = beta = 1."""
+    log("bench: square sweep, FP64 and FP32")
+    stream = torch.cuda.current_stream()
+    out = {"inputs": "uniform[-1,1) on the device, alpha = beta = 1", "f64": {}, "f32": {}}
+    for name, tdt, dt, peak in (("f64", torch.float64, mg.F64, PEAK_F64_TFLOPS),
+                                ("f32", torch.float32, mg.F32, PEAK_F32_TFLOPS)):
+        for n in sizes:
+            g = torch.Generator(device=dev)
+            g.manual_seed(7000 + n)
+            A = torch.rand((n, n), device=dev, dtype=tdt, generator=g) * 2 - 1
+            B = torch.rand((n, n), device=dev, dtype=tdt, generator=g) * 2 - 1
+            C = torch.rand((n, n), device=dev, dtype=tdt, generator=g) * 2 - 1
+            reps = 10 if n <= 8192 else 3
+            ts = timed(lambda: mg.gemm(A, B, C, 1.0, 1.0, stream=stream), stream, reps)
+            ms = float(np.mean(ts))
+            tf = 2.0 * n ** 3 / ms / 1e9
+            out[name][str(n)] = {"ms": round(ms, 4), "tflops": round(tf, 3),
+                                 "pct_peak": round(100 * tf / peak, 2),
+                                 "best_tflops": round(2.0 * n ** 3 / min(ts) / 1e9, 3)}
+            log(f"  {name} N={n}: {ms:.3f} ms, {tf:.1f} TFLOP/s")
+            del A, B, C
+        torch.cuda.empty_cache()
     return out
 
 
@@ -236,6 +263,7 @@ def main():
     n = args.n
     if args.leg:
         legs = {"split": lambda: leg_split(mg, torch, dev, n),
+                "sweep": lambda: leg_sweep(mg, torch, dev),
                 "batched": lambda: leg_batched(mg, torch, dev),
                 "tuner": lambda: leg_tuner(mg)}
         print(json.dumps({args.leg: legs[args.leg]()}), flush=True)
@@ -333,7 +361,8 @@ def main():
         "cpu_baseline": cpu,
     }
     if not args.no_extras:
-        for name, fn in (("split", lambda: leg_split(mg, torch, dev)),
+        for name, fn in (("sweep", lambda: leg_sweep(mg, torch, dev)),
+                         ("split", lambda: leg_split(mg, torch, dev)),
                          ("batched", lambda: leg_batched(mg, torch, dev)),
                          ("tuner", lambda: leg_tuner(mg))):
             try:

@@ -24,7 +24,6 @@
 // same operand width), this needs 16 products of the full width, each a plain
 // int8 GEMM.
 #include <limits.h>
-#include <stdlib.h>
 
 #include "mgemm_internal.h"
 
@@ -147,20 +146,28 @@ crt_residue_b_kernel(const double *__restrict__ B, int64_t k, int64_t n, int64_t
 // ---------------------------------------------------------------------------
 // Work-group: WGM x WGN waves own a 256 x 256 tile of C for one modulus; each
 // wave a (256/WGM) x (256/WGN) block as 32x32 accumulators of the 32x32x32 int8
-// MFMA.  A stage holds 64 k of the tile's 256 A rows and 256 B columns (rows of
-// 4 data units of 16 bytes plus one pad unit, so the fragment reads of 16
-// consecutive rows hit distinct banks); four stages are filled by direct
-// global->LDS loads three stages ahead, and every fragment register is refilled
-// from the next stage right after its last use.  Operands are zero-padded to
-// whole tiles and stages, so no load or store needs a bounds test.
+// MFMA.  A stage holds 64 k of the tile's 256 A rows and 256 B columns; the
+// stages are filled by direct global->LDS loads NST-1 stages ahead, and every
+// fragment register is refilled from the next stage right after its last use.
+// Operands are zero-padded to whole tiles and stages, so no load or store needs
+// a bounds test.
 constexpr int G_KS = CRT_KSTEP;                 // k per stage
-constexpr int G_ROW = G_KS / 16 + 1;            // units per LDS row
-constexpr int G_AUNITS = CRT_TILE * G_ROW;      // A part of a stage (units)
-constexpr int G_STAGE = 2 * G_AUNITS;           // units per stage
-constexpr int G_NST = 4;                        // stages
 constexpr int G_PASS = (1 << 16) / G_KS;        // stages per launch: |acc| < 2^16 * 2^14
-static_assert(G_AUNITS % 64 == 0, "a wave's loads lie in one operand");
-static_assert(G_NST * G_STAGE * 16 <= 163840, "LDS");
+
+// LDS layout of one stage: 256 A rows then 256 B rows of 64 k (4 units of 16 B).
+//  PADDED:   rows of 5 units (the fifth a copy, never read); four stages.
+//  SWIZZLED: rows of 4 units, logical unit c of row r stored at c ^ sw(r) with
+//            sw(r) = ((r >> 1) ^ (r >> 3)) & 3; five stages in the same space.
+// Both make the fragment reads of consecutive rows hit distinct banks.
+template <bool SWZ> struct StageLayout {
+    static constexpr int ROW = SWZ ? 4 : 5;                 // units per LDS row
+    static constexpr int AUNITS = CRT_TILE * ROW;           // A part of a stage
+    static constexpr int STAGE = 2 * AUNITS;                // units per stage
+    static constexpr int NST = SWZ ? 5 : 4;                 // stages
+    static_assert(AUNITS % 64 == 0, "a wave's loads lie in one operand");
+    static_assert(NST * STAGE * 16 <= 163840, "LDS");
+    __device__ static int sw(int r) { return SWZ ? ((r >> 1) ^ (r >> 3)) & 3 : 0; }
+};
 
 // s_waitcnt immediate: vmcnt(n), no wait on the other counters
 constexpr int vmcnt_imm(int n) { return (n & 15) | ((n >> 4) << 14) | 0x70 | 0xF00; }
@@ -179,15 +186,17 @@ struct CrtGemmArgs {
 // 32x32 accumulator element r of lane l: row 8(r/4) + 4(l/32) + r%4, column l%32.
 __device__ inline int crt_acc_row(int lane, int r) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }
 
-template <int WGM, int WGN>
+template <int WGM, int WGN, bool SWZ>
 __global__ void __launch_bounds__(64 * WGM * WGN) __attribute__((amdgpu_waves_per_eu(WGM * WGN / 4)))
 crt_gemm_kernel(CrtGemmArgs a) {
+    typedef StageLayout<SWZ> L;
     constexpr int NT = 64 * WGM * WGN;
     constexpr int WTM = CRT_TILE / WGM, WTN = CRT_TILE / WGN;   // wave block
     constexpr int FM = WTM / 32, FN = WTN / 32;                 // accumulators per wave
-    constexpr int LOADS = G_STAGE / NT;                         // loads per lane per stage
-    static_assert(G_STAGE % NT == 0, "load split");
-    __shared__ u32x4 lds[G_NST * G_STAGE];
+    constexpr int LOADS = L::STAGE / NT;                        // loads per lane per stage
+    constexpr int NST = L::NST;
+    static_assert(L::STAGE % NT == 0, "load split");
+    __shared__ u32x4 lds[NST * L::STAGE];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wm = wave / WGN, wn = wave % WGN;
@@ -207,13 +216,15 @@ crt_gemm_kernel(CrtGemmArgs a) {
     const int8_t *qa = a.QA + t * a.plane_a + (int64_t)tm * CRT_TILE * a.kp;
     const int8_t *qb = a.QB + t * a.plane_b + (int64_t)tn * CRT_TILE * a.kp;
 
+    // per-lane source offsets: LDS unit u of a stage holds row r, logical unit c
     uint32_t off[LOADS];
 #pragma unroll
     for (int i = 0; i < LOADS; ++i) {
         const int u = i * NT + wave * 64 + lane;
-        const int v = u < G_AUNITS ? u : u - G_AUNITS;
-        const int r = v / G_ROW, c = v % G_ROW;
-        off[i] = (uint32_t)r * (uint32_t)a.kp + (uint32_t)(c < G_ROW - 1 ? c : G_ROW - 2) * 16u;
+        const int v = u < L::AUNITS ? u : u - L::AUNITS;
+        const int r = v / L::ROW, pu = v % L::ROW;
+        const int c = SWZ ? (pu ^ L::sw(r)) : (pu < 4 ? pu : 3);
+        off[i] = (uint32_t)r * (uint32_t)a.kp + (uint32_t)c * 16u;
     }
     auto issue = [&](int chunk, int st) {
         const int8_t *sa = qa + (int64_t)chunk * G_KS;
@@ -221,9 +232,9 @@ crt_gemm_kernel(CrtGemmArgs a) {
 #pragma unroll
         for (int i = 0; i < LOADS; ++i) {
             const int first = i * NT + wave * 64;                 // uniform per wave
-            const int8_t *src = (first < G_AUNITS ? sa : sb) + off[i];
+            const int8_t *src = (first < L::AUNITS ? sa : sb) + off[i];
             __builtin_amdgcn_global_load_lds((const void *)src,
-                                             (__attribute__((address_space(3))) void *)(lds + st * G_STAGE + first),
+                                             (__attribute__((address_space(3))) void *)(lds + st * L::STAGE + first),
                                              16, 0, 0);
         }
     };
@@ -234,14 +245,21 @@ crt_gemm_kernel(CrtGemmArgs a) {
 #pragma unroll
         for (int j = 0; j < FN; ++j) acc[i][j] = v16i{};
 
-    const int a_unit = (wm * WTM + (lane & 31)) * G_ROW + (lane >> 5);
-    const int b_unit = G_AUNITS + (wn * WTN + (lane & 31)) * G_ROW + (lane >> 5);
+    // fragment rows of this lane: the swizzle is the same for rows 32 apart
+    const int ra = wm * WTM + (lane & 31), rb = wn * WTN + (lane & 31);
+    int a_unit[2], b_unit[2];
+#pragma unroll
+    for (int kk = 0; kk < 2; ++kk) {
+        const int c = kk * 2 + (lane >> 5);
+        a_unit[kk] = ra * L::ROW + (c ^ L::sw(ra));
+        b_unit[kk] = L::AUNITS + rb * L::ROW + (c ^ L::sw(rb));
+    }
     v4i fa[2][FM], fb[2][FN];
     auto read_a = [&](const u32x4 *st, int kk, int mt) {
-        fa[kk][mt] = __builtin_bit_cast(v4i, st[a_unit + mt * 32 * G_ROW + kk * 2]);
+        fa[kk][mt] = __builtin_bit_cast(v4i, st[a_unit[kk] + mt * 32 * L::ROW]);
     };
     auto read_b = [&](const u32x4 *st, int kk, int nt) {
-        fb[kk][nt] = __builtin_bit_cast(v4i, st[b_unit + nt * 32 * G_ROW + kk * 2]);
+        fb[kk][nt] = __builtin_bit_cast(v4i, st[b_unit[kk] + nt * 32 * L::ROW]);
     };
     // products of one stage; each fragment is refilled from the next stage right
     // after its last use (past the last stage the refills read a stale stage and
@@ -264,15 +282,14 @@ crt_gemm_kernel(CrtGemmArgs a) {
         }
     };
 
-    // stages of this pass, counted from its first; chunks 0..2 in flight, wait for
-    // chunk 0 (two chunks' loads may remain)
+    // stages of this pass, counted from its first.  Chunks 0..NST-2 in flight;
+    // wait for chunk 0 (the loads of NST-2 chunks may remain)
     qa += (int64_t)a.ch0 * G_KS;
     qb += (int64_t)a.ch0 * G_KS;
     const int nst = a.ch1 - a.ch0;
-    issue(0, 0);
-    issue(nst > 1 ? 1 : nst - 1, 1);
-    issue(nst > 2 ? 2 : nst - 1, 2);
-    __builtin_amdgcn_s_waitcnt(vmcnt_imm(2 * LOADS));
+#pragma unroll
+    for (int c = 0; c < NST - 1; ++c) issue(c < nst ? c : nst - 1, c);
+    __builtin_amdgcn_s_waitcnt(vmcnt_imm((NST - 2) * LOADS));
     __syncthreads();
 #pragma unroll
     for (int kk = 0; kk < 2; ++kk) {
@@ -283,13 +300,15 @@ crt_gemm_kernel(CrtGemmArgs a) {
     }
     int st = 0;                                   // stage of chunk c
     for (int c = 0; c < nst; ++c) {
-        __builtin_amdgcn_s_waitcnt(vmcnt_imm(LOADS));   // chunk c+1 has landed
+        // chunk c+1 has landed (the loads of NST-3 later chunks may remain)
+        __builtin_amdgcn_s_waitcnt(vmcnt_imm((NST - 3) * LOADS));
         __syncthreads();
-        const int st1 = (st + 1) & 3;
-        // chunk c+3 into the stage of chunk c-1 (past the end: the last chunk
+        const int st1 = st + 1 == NST ? 0 : st + 1;
+        const int stn = st == 0 ? NST - 1 : st - 1;    // stage of chunk c-1
+        // chunk c+NST-1 into the stage of chunk c-1 (past the end: the last chunk
         // again, in bounds and never used)
-        issue(c + 3 < nst ? c + 3 : nst - 1, (st + 3) & 3);
-        products(lds + st1 * G_STAGE);
+        issue(c + NST - 1 < nst ? c + NST - 1 : nst - 1, stn);
+        products(lds + st1 * L::STAGE);
         st = st1;
     }
     __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));       // no load lands after this point
@@ -483,17 +502,17 @@ hipError_t crt_launch(const GemmArgs &g, hipStream_t s, const int *e, const int 
         ga.tiles_n = (int)(np / CRT_TILE);
         const int64_t nstages = kp / CRT_KSTEP;
         const int64_t blocks = (int64_t)ga.tiles_m * ga.tiles_n * CRT_MODULI;
-        static const int waves = getenv("MGEMM_CRT_WAVES") ? atoi(getenv("MGEMM_CRT_WAVES")) : 4;
         // passes of at most 2^16 k keep the int32 sums exact; later passes add
         // their residues to the stored ones
         for (int64_t c0 = 0; c0 < nstages; c0 += G_PASS) {
             ga.ch0 = (int)c0;
             ga.ch1 = (int)(c0 + G_PASS < nstages ? c0 + G_PASS : nstages);
             ga.accumulate = c0 > 0;
-            if (waves == 8)
-                hipLaunchKernelGGL((crt_gemm_kernel<2, 4>), dim3((unsigned)blocks), dim3(512), 0, s, ga);
-            else
-                hipLaunchKernelGGL((crt_gemm_kernel<2, 2>), dim3((unsigned)blocks), dim3(256), 0, s, ga);
+            // 8 waves of 128 x 64 (two per SIMD) measured faster than 4 waves of
+            // 128 x 128 (one per SIMD), which spend more time exposed at the barrier
+            // (the swizzled five-stage layout measured 3 % faster than the padded
+            // four-stage one)
+            hipLaunchKernelGGL((crt_gemm_kernel<2, 4, true>), dim3((unsigned)blocks), dim3(512), 0, s, ga);
         }
     }
     {
