@@ -226,17 +226,17 @@ crt_gemm_kernel(CrtGemmArgs a) {
         const int c = SWZ ? (pu ^ L::sw(r)) : (pu < 4 ? pu : 3);
         off[i] = (uint32_t)r * (uint32_t)a.kp + (uint32_t)c * 16u;
     }
+    // load instruction i of chunk `chunk` into stage st
+    auto issue_one = [&](int i, int chunk, int st) {
+        const int first = i * NT + wave * 64;                     // uniform per wave
+        const int8_t *src = (first < L::AUNITS ? qa : qb) + (int64_t)chunk * G_KS + off[i];
+        __builtin_amdgcn_global_load_lds((const void *)src,
+                                         (__attribute__((address_space(3))) void *)(lds + st * L::STAGE + first),
+                                         16, 0, 0);
+    };
     auto issue = [&](int chunk, int st) {
-        const int8_t *sa = qa + (int64_t)chunk * G_KS;
-        const int8_t *sb = qb + (int64_t)chunk * G_KS;
 #pragma unroll
-        for (int i = 0; i < LOADS; ++i) {
-            const int first = i * NT + wave * 64;                 // uniform per wave
-            const int8_t *src = (first < L::AUNITS ? sa : sb) + off[i];
-            __builtin_amdgcn_global_load_lds((const void *)src,
-                                             (__attribute__((address_space(3))) void *)(lds + st * L::STAGE + first),
-                                             16, 0, 0);
-        }
+        for (int i = 0; i < LOADS; ++i) issue_one(i, chunk, st);
     };
 
     v16i acc[FM][FN];
@@ -264,7 +264,10 @@ crt_gemm_kernel(CrtGemmArgs a) {
     // products of one stage; each fragment is refilled from the next stage right
     // after its last use (past the last stage the refills read a stale stage and
     // are never used)
-    auto products = [&](const u32x4 *nst) {
+    // The stage's loads (chunk lc into stage ls) are spread over the products, one
+    // after every 2*FM/LOADS fragment rows, so that the memory pipeline takes them
+    // a few at a time instead of all waves queueing every load at the barrier.
+    auto products = [&](const u32x4 *nst, int lc, int ls) {
 #pragma unroll
         for (int kk = 0; kk < 2; ++kk) {
 #pragma unroll
@@ -274,6 +277,10 @@ crt_gemm_kernel(CrtGemmArgs a) {
                     acc[mt][nt] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[kk][mt], fb[kk][nt],
                                                                          acc[mt][nt], 0, 0, 0);
                 read_a(nst, kk, mt);
+                constexpr int every = 2 * FM / LOADS > 0 ? 2 * FM / LOADS : 1;
+                static_assert((LOADS - 1) * every < 2 * FM, "every load gets a slot");
+                const int slot = kk * FM + mt;
+                if (slot % every == 0 && slot / every < LOADS) issue_one(slot / every, lc, ls);
                 __builtin_amdgcn_sched_barrier(0);
             }
 #pragma unroll
@@ -307,8 +314,7 @@ crt_gemm_kernel(CrtGemmArgs a) {
         const int stn = st == 0 ? NST - 1 : st - 1;    // stage of chunk c-1
         // chunk c+NST-1 into the stage of chunk c-1 (past the end: the last chunk
         // again, in bounds and never used)
-        issue(c + NST - 1 < nst ? c + NST - 1 : nst - 1, stn);
-        products(lds + st1 * L::STAGE);
+        products(lds + st1 * L::STAGE, c + NST - 1 < nst ? c + NST - 1 : nst - 1, stn);
         st = st1;
     }
     __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));       // no load lands after this point

@@ -460,19 +460,20 @@ __global__ void __launch_bounds__(64 * WGM * WGN)
     }
     const char *Apanel = (const char *)(A + m0 * lda);
     const char *Bpanel = (const char *)(B + n0);
+    // load instruction i of k-step kstep into stage
+    auto issue_one = [&](int i, int64_t kstep, u32x4_t *stage) {
+        const int first = i * S::NT + wave * 64;
+        // only the last instruction can run past the stage (uniform per wave)
+        if ((i + 1) * S::NT > S::STAGE && first >= S::STAGE) return;
+        const char *src = first < S::A_UNITS ? Apanel + kstep * (BK * (int64_t)sizeof(T))
+                                             : Bpanel + kstep * (BK * ldb * (int64_t)sizeof(T));
+        __builtin_amdgcn_global_load_lds((const void *)(src + src_off[i]),
+                                         (__attribute__((address_space(3))) void *)(stage + first),
+                                         16, 0, 0);
+    };
     auto issue = [&](int64_t kstep, u32x4_t *stage) {
-        const char *a_src = Apanel + kstep * (BK * (int64_t)sizeof(T));
-        const char *b_src = Bpanel + kstep * (BK * ldb * (int64_t)sizeof(T));
 #pragma unroll
-        for (int i = 0; i < S::LOADS; ++i) {
-            const int first = i * S::NT + wave * 64;
-            // only the last instruction can run past the stage (uniform per wave)
-            if ((i + 1) * S::NT > S::STAGE && first >= S::STAGE) continue;
-            const char *src = (first < S::A_UNITS ? a_src : b_src) + src_off[i];
-            __builtin_amdgcn_global_load_lds((const void *)src,
-                                             (__attribute__((address_space(3))) void *)(stage + first),
-                                             16, 0, 0);
-        }
+        for (int i = 0; i < S::LOADS; ++i) issue_one(i, kstep, stage);
     };
 
     acc4 acc[S::FM][S::FN];
@@ -500,7 +501,13 @@ __global__ void __launch_bounds__(64 * WGM * WGN)
     // products of one k-step; each fragment is refilled from the next stage right
     // after its last use (past the last k-step the refills read a stale stage and
     // are never used)
-    auto products = [&](const u32x4_t *nst) {
+    // The k-step's loads (k-step lk into stage lst) are spread over the products,
+    // one every few fragment rows, so the memory pipeline takes a few at a time
+    // instead of every wave queueing all of them at the barrier.
+    auto products = [&](const u32x4_t *nst, int64_t lk, u32x4_t *lst) {
+        constexpr int SLOTS = S::G * 2 * S::FM;
+        constexpr int EVERY = SLOTS / S::LOADS > 0 ? SLOTS / S::LOADS : 1;
+        static_assert((S::LOADS - 1) * EVERY < SLOTS, "every load gets a slot");
 #pragma unroll
         for (int g = 0; g < S::G; ++g) {
 #pragma unroll
@@ -510,10 +517,10 @@ __global__ void __launch_bounds__(64 * WGM * WGN)
 #pragma unroll
                     for (int j = 0; j < S::FN; ++j)
                         acc[i][j] = E::mma(af[g][i][h], bf[g][h][j], acc[i][j]);
-                    if (h == 1) {
-                        read_a(nst, g, i);
-                        __builtin_amdgcn_sched_barrier(0);
-                    }
+                    if (h == 1) read_a(nst, g, i);
+                    const int slot = (g * 2 + h) * S::FM + i;
+                    if (slot % EVERY == 0 && slot / EVERY < S::LOADS) issue_one(slot / EVERY, lk, lst);
+                    if (h == 1 || slot % EVERY == 0) __builtin_amdgcn_sched_barrier(0);
                 }
                 read_b(nst, g, h);
                 __builtin_amdgcn_sched_barrier(0);
@@ -543,8 +550,7 @@ __global__ void __launch_bounds__(64 * WGM * WGN)
             __syncthreads();
             const int st1 = st == 2 ? 0 : st + 1;
             const int st2 = st1 == 2 ? 0 : st1 + 1;
-            issue(c + 2 < nk ? c + 2 : nk - 1, lds + st2 * S::STAGE);
-            products(lds + st1 * S::STAGE);
+            products(lds + st1 * S::STAGE, c + 2 < nk ? c + 2 : nk - 1, lds + st2 * S::STAGE);
             st = st1;
         }
         __builtin_amdgcn_s_waitcnt(0x0F70);      // no load may land after this point
