@@ -122,8 +122,9 @@ MGEMM_API int32_t gemm(int64_t m, int64_t n, int64_t k, double alpha,
  * exact C'_ij = sum_p A'_ip B'_pj is obtained from 16 int8 GEMMs of their
  * residues modulo 16 pairwise coprime moduli (Chinese remainder theorem), rounded
  * once to FP64, scaled by 2^(e_i+f_j-2b), and C = alpha*v + beta*C.  k is limited
- * to 2^40; the workspace (same rules as above) holds about 16*((m+n)*k + m*n)
- * bytes.  Non-finite input: MGEMM_ERR_NONFINITE, C untouched.  cfg must be NULL. */
+ * to 2^24 - 64 (MGEMM_ERR_NOCONFIG above); the workspace (same rules as above)
+ * holds about 16*((m+n)*k + m*n) bytes.  Non-finite input: MGEMM_ERR_NONFINITE, C
+ * untouched.  cfg must be NULL. */
 MGEMM_API int32_t gemm_ex(int64_t m, int64_t n, int64_t k, double alpha,
                 const void *A, int64_t lda, const void *B, int64_t ldb,
                 double beta, void *C, int64_t ldc, int32_t dtype,

@@ -732,13 +732,11 @@ static int32_t run_split(const GemmArgs &g, hipStream_t s, Workspace &w, int max
 // Modular-integer emulation: the scale step above, then the residue, product and
 // reconstruction kernels of crt.hip on the same workspace.
 static int32_t run_crt(const GemmArgs &g, hipStream_t s, Workspace &w) {
-    if (g.k > ((int64_t)1 << 40))
-        return set_error(MGEMM_ERR_NOCONFIG, "crt int8: k above 2^40");
     const int64_t mp = round_up(g.m, CRT_TILE), np = round_up(g.n, CRT_TILE),
                   kp = round_up(g.k, CRT_KSTEP);
     // the product kernel addresses a tile's rows of one plane with 32-bit offsets
     if ((double)CRT_TILE * (double)kp >= 4294967296.0)
-        return set_error(MGEMM_ERR_NOCONFIG, "crt int8: k too large for one plane");
+        return set_error(MGEMM_ERR_NOCONFIG, "crt int8: k above 2^24 - 64");
     const size_t qa_bytes = (size_t)CRT_MODULI * mp * kp, qb_bytes = (size_t)CRT_MODULI * np * kp;
     const size_t r_bytes = (size_t)CRT_MODULI * mp * np;
     const size_t e_bytes = round_up(mp * 4, 256), f_bytes = round_up(np * 4, 256);

@@ -64,3 +64,25 @@ def test_predictions_are_valid_configurations(data):
         mg.gemm(a, b, out, 1.0, 0.0, cfg=cfg)
         torch.cuda.synchronize()
         assert torch.all(out == 5.0)
+
+
+def test_chooser_database_then_model():
+    """The run-time chooser: a swept shape takes its database best, an unseen
+    shape the model's prediction; the product is correct either way."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1706_10086_amd import choose
+    ch = choose.ConfigChooser()
+    seen = tune.shape_set("heldout")[0]
+    for (m, n, k), want in ((seen, "database"), ((333, 517, 271), "model")):
+        print(f"chooser shape {(m, n, k)}", flush=True)
+        g = torch.Generator().manual_seed(m + n + k)
+        A = torch.rand((m, k), generator=g, dtype=torch.float64)
+        B = torch.rand((k, n), generator=g, dtype=torch.float64)
+        C = torch.zeros((m, n), dtype=torch.float64, device="cuda")
+        _, source = choose.tuned_gemm(A.cuda(), B.cuda(), C, chooser=ch)
+        torch.cuda.synchronize()
+        assert source == want
+        ref = A @ B
+        err = float(torch.linalg.norm(C.cpu() - ref) / torch.linalg.norm(ref))
+        assert err <= 1e-13
