@@ -166,8 +166,10 @@ constexpr int G_PASS = (1 << 16) / G_KS;        // stages per launch: |acc| < 2^
 // LDS layout of one stage: 256 A rows then 256 B rows of 64 k (4 units of 16 B).
 //  PADDED:   rows of 5 units (the fifth a copy, never read); four stages.
 //  SWIZZLED: rows of 4 units, logical unit c of row r stored at c ^ sw(r) with
-//            sw(r) = ((r >> 1) ^ (r >> 3)) & 3; five stages in the same space.
-// Both make the fragment reads of consecutive rows hit distinct banks.
+//            sw(r) = (r >> 2) & 3; five stages in the same space.
+// Both keep the fragment reads free of bank conflicts (SQ_LDS_BANK_CONFLICT reads
+// 0 for either; of the XOR patterns tried, (r >> 1) & 3 or ((r >> 1) ^ (r >> 3)) & 3
+// conflict on half of the LDS cycles, r & 3 on three quarters).
 template <bool SWZ> struct StageLayout {
     static constexpr int ROW = SWZ ? 4 : 5;                 // units per LDS row
     static constexpr int AUNITS = CRT_TILE * ROW;           // A part of a stage
@@ -175,7 +177,7 @@ template <bool SWZ> struct StageLayout {
     static constexpr int NST = SWZ ? 5 : 4;                 // stages
     static_assert(AUNITS % 64 == 0, "a wave's loads lie in one operand");
     static_assert(NST * STAGE * 16 <= 163840, "LDS");
-    __device__ static int sw(int r) { return SWZ ? ((r >> 1) ^ (r >> 3)) & 3 : 0; }
+    __device__ static int sw(int r) { return SWZ ? (r >> 2) & 3 : 0; }
 };
 
 // s_waitcnt immediate: vmcnt(n), no wait on the other counters
