@@ -55,7 +55,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extras", action="store_true", help="only the FP64 headline leg")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--leg", choices=["sweep", "split", "batched", "tuner"], default=None,
+    ap.add_argument("--leg", choices=["parity", "sweep", "split", "batched", "tuner"], default=None,
                     help="run only this extra leg and print its JSON (for profiling runs)")
     return ap.parse_args()
 
@@ -93,13 +93,22 @@ def cpu_baseline(n, A, B, C, budget_s):
     oracle.gemm_f64(1.0, A[:rows], B, 1.0, C[:rows], nthreads=cores)
     dt = time.perf_counter() - t
     flops = 2.0 * rows * n * n
+    # one thread on the whole N = 1024 product, extrapolated by N^3 to this N
+    import synth
+    a1 = synth.uniform_pm1((1024, 1024), 9001)
+    b1 = synth.uniform_pm1((1024, 1024), 9002)
+    t1 = time.perf_counter()
+    oracle.gemm_f64(1.0, a1, b1, 0.0, None, nthreads=1)
+    t1 = time.perf_counter() - t1
     return {"value": round(flops / dt / 1e12, 5), "unit": "TFLOP/s", "cores": cores,
             "kind": "oracle",
             "sample": f"first {rows} of {n} rows of the N={n} FP64 product "
-                      f"({flops / 1e9:.1f} GFLOP in {dt:.1f} s, OpenMP over rows)"}
+                      f"({flops / 1e9:.1f} GFLOP in {dt:.1f} s, OpenMP over rows)",
+            "single_thread_n1024_s": round(t1, 3),
+            "single_thread_extrapolated_s": round(t1 * (n / 1024) ** 3, 1)}
 
 
-def leg_split(mg, torch, dev, n=8192):
+def leg_split(mg, torch, dev, n=8192, with_small=True):
     import oracle
     import synth
     log(f"bench: split leg, N={n} wide-range inputs")
@@ -132,7 +141,54 @@ def leg_split(mg, torch, dev, n=8192):
     out["crt_int8"]["mfma_util"] = round(16 * 2.0 * npad * npad * kpad /
                                          (out["crt_int8"]["ms"] * 1e9) / PEAK_INT8_TOPS, 4)
     del tA, tB, tC
+    torch.cuda.empty_cache()
+    if not with_small:
+        return out
+    # the smaller split size, same recipe
+    m = n // 2
+    sa, sb, _ = synth.seeds_for(2, int(np.log2(m)))
+    A = synth.wide_range((m, m), sa)
+    B = synth.wide_range((m, m), sb)
+    tA, tB = torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev)
+    tC = torch.zeros((m, m), device=dev, dtype=torch.float64)
+    rows = np.array([0, 1, 1000, 2222, 3000, m - 1])
+    ref = oracle.gemm_dot2(1.0, A[rows], B, nthreads=oracle.num_procs())
+    small = {"n": m}
+    for name, dt in (("f64", mg.F64), ("bf16", mg.SPLIT_BF16), ("int8", mg.SPLIT_INT8),
+                     ("crt_int8", mg.CRT_INT8)):
+        ts = timed(lambda: mg.gemm(tA, tB, tC, 1.0, 0.0, dtype=dt, stream=stream), stream, 5)
+        got = tC[torch.from_numpy(rows).to(dev)].cpu().numpy()
+        ms = float(np.mean(ts))
+        small[name] = {"ms": round(ms, 4), "tflops_fp64_equiv": round(2.0 * m ** 3 / ms / 1e9, 3),
+                       "rel_err": float(np.linalg.norm(got - ref) / np.linalg.norm(ref))}
+        log(f"  n={m} {name}: {ms:.3f} ms, err {small[name]['rel_err']:.2e}")
+    out[f"n{m}"] = small
+    del tA, tB, tC
     return out
+
+
+def leg_parity(mg, torch, dev):
+    """The parity case: m = n = k = 256, uniform inputs, alpha 1.5, beta 0.5; the
+    GPU time (latency-bound), the oracle's single-thread wall time and the
+    normwise error against it."""
+    import oracle
+    import synth
+    n = 256
+    sa, sb, sc = synth.seeds_for(0, 8)
+    A, B, C = synth.uniform_pm1((n, n), sa), synth.uniform_pm1((n, n), sb), synth.uniform_pm1((n, n), sc)
+    tA, tB, tC0 = (torch.from_numpy(x).to(dev) for x in (A, B, C))
+    tC = tC0.clone()
+    stream = torch.cuda.current_stream()
+    mg.gemm(tA, tB, tC, 1.5, 0.5, stream=stream)
+    got = tC.cpu().numpy()
+    t = time.perf_counter()
+    want = oracle.gemm_f64(1.5, A, B, 0.5, C, nthreads=1)
+    t_orc = time.perf_counter() - t
+    ts = timed(lambda: mg.gemm(tA, tB, tC, 1.5, 0.5, stream=stream), stream, 50, warmup=5)
+    return {"n": n, "gpu_us": round(1e3 * float(np.mean(ts)), 2),
+            "gpu_tflops": round(2.0 * n ** 3 / float(np.mean(ts)) / 1e9, 3),
+            "oracle_single_thread_s": round(t_orc, 4),
+            "rel_err": float(np.linalg.norm(got - want) / np.linalg.norm(want))}
 
 
 def leg_sweep(mg, torch, dev, sizes=(1024, 2048, 4096, 8192, 16384)):
@@ -183,12 +239,43 @@ def leg_batched(mg, torch, dev):
     tl = timed(lambda: mg.gemm_batched(As, Bs, Cs, 1.0, 0.0), stream, 3, warmup=1)
     info = plan.info()
     plan.destroy()
-    return {"problems": cnt, "flops": flops, "buckets": info["buckets"], "tiles": info["tiles"],
-            "graph_ms": round(float(np.mean(tp)), 4),
-            "graph_tflops": round(flops / float(np.mean(tp)) / 1e9, 3),
-            "per_problem_ms": round(float(np.mean(tl)), 4),
-            "per_problem_tflops": round(flops / float(np.mean(tl)) / 1e9, 3),
-            "speedup": round(float(np.mean(tl)) / float(np.mean(tp)), 3)}
+    nbytes = float(sum(8.0 * (m * k + k * n + m * n) for m, n, k in zip(ms, ns, ks)))
+    gms = float(np.mean(tp))
+    out = {"problems": cnt, "flops": flops, "bytes": nbytes, "buckets": info["buckets"],
+           "tiles": info["tiles"], "graph_ms": round(gms, 4),
+           "graph_tflops": round(flops / gms / 1e9, 3),
+           # max(sum F / peak, sum B / bandwidth) / t: the batch's roofline fraction
+           "roofline_frac": round(max(flops / (PEAK_F64_TFLOPS * 1e12), nbytes / 8e12) / (gms * 1e-3), 4),
+           "per_problem_ms": round(float(np.mean(tl)), 4),
+           "per_problem_tflops": round(flops / float(np.mean(tl)) / 1e9, 3),
+           "speedup": round(float(np.mean(tl)) / gms, 3)}
+    # the oracle on every problem of the batch, all host cores (the first 512
+    # problems, scaled by FLOP to the whole batch)
+    import oracle
+    sub = 512
+    t = time.perf_counter()
+    for i in range(sub):
+        oracle.gemm_f64(1.0, As[i].cpu().numpy(), Bs[i].cpu().numpy(), 0.0, None,
+                        nthreads=oracle.num_procs())
+    t_sub = time.perf_counter() - t
+    f_sub = float(sum(2.0 * m * n * k for m, n, k in zip(ms[:sub], ns[:sub], ks[:sub])))
+    out["oracle_batch_s_estimate"] = round(t_sub * flops / f_sub, 2)
+    # FP32 variant of the same batch
+    As32 = [a.float() for a in As]
+    Bs32 = [b.float() for b in Bs]
+    Cs32 = [c.float() for c in Cs]
+    del As, Bs, Cs
+    plan = mg.BatchedPlan(As32, Bs32, Cs32, 1.0, 0.0, stream=stream)
+    tp = timed(plan.execute, stream, 10, warmup=2)
+    tl = timed(lambda: mg.gemm_batched(As32, Bs32, Cs32, 1.0, 0.0), stream, 3, warmup=1)
+    plan.destroy()
+    g32 = float(np.mean(tp))
+    out["f32"] = {"graph_ms": round(g32, 4), "graph_tflops": round(flops / g32 / 1e9, 3),
+                  "roofline_frac": round(max(flops / (PEAK_F32_TFLOPS * 1e12), nbytes / 2 / 8e12) /
+                                         (g32 * 1e-3), 4),
+                  "per_problem_ms": round(float(np.mean(tl)), 4),
+                  "speedup": round(float(np.mean(tl)) / g32, 3)}
+    return out
 
 
 def live_recheck(mg, pred, table, count=12):
@@ -262,8 +349,10 @@ def main():
     dev = torch.device("cuda:0")
     n = args.n
     if args.leg:
-        legs = {"split": lambda: leg_split(mg, torch, dev, n),
+        # (a profiling run of one leg: the split leg at N only)
+        legs = {"split": lambda: leg_split(mg, torch, dev, n, with_small=False),
                 "sweep": lambda: leg_sweep(mg, torch, dev),
+                "parity": lambda: leg_parity(mg, torch, dev),
                 "batched": lambda: leg_batched(mg, torch, dev),
                 "tuner": lambda: leg_tuner(mg)}
         print(json.dumps({args.leg: legs[args.leg]()}), flush=True)
@@ -361,7 +450,8 @@ def main():
         "cpu_baseline": cpu,
     }
     if not args.no_extras:
-        for name, fn in (("sweep", lambda: leg_sweep(mg, torch, dev)),
+        for name, fn in (("parity", lambda: leg_parity(mg, torch, dev)),
+                         ("sweep", lambda: leg_sweep(mg, torch, dev)),
                          ("split", lambda: leg_split(mg, torch, dev)),
                          ("batched", lambda: leg_batched(mg, torch, dev)),
                          ("tuner", lambda: leg_tuner(mg))):
