@@ -415,71 +415,6 @@ split_pairs_bf16_kernel(PairArgs a) {
     }
 }
 
-// int8: eight int32 level accumulators (exact for k <= 16384 per pass), combined
-// exactly at the end into hi (levels 2-5, units of level 5) and lo (levels 6-9,
-// units of level 9).
-__global__ void __launch_bounds__(512)
-split_pairs_i8_kernel(PairArgs a) {
-    typedef FmtI8 F;
-    typedef PairTile<F> P;
-    __shared__ u32x4 sA[2][PBM * P::SROW];
-    __shared__ u32x4 sB[2][PBN * P::SROW];
-
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave >> 2, wn = wave & 3;
-    int tm, tn;
-    tile_of_block(blockIdx.x, gridDim.x, a.tiles_m, a.tiles_n, tm, tn);
-    const int64_t m0 = (int64_t)tm * PBM, n0 = (int64_t)tn * PBN;
-
-    v16i acc[8];
-#pragma unroll
-    for (int l = 0; l < 8; ++l) acc[l] = v16i{};
-
-    const int r32 = lane & 31, kh = lane >> 5;
-    const int a_off = (wm * 32 + r32) * P::SROW + kh;
-    const int b_off = (wn * 32 + r32) * P::SROW + kh;
-
-    u32x4 stage[P::LOADS];
-    pair_load<F>(a, m0, n0, a.ch0, stage);
-    pair_store<F>(sA[0], sB[0], stage);
-    __syncthreads();
-
-    for (int64_t ch = a.ch0; ch < a.ch1; ++ch) {
-        const int cur = (int)((ch - a.ch0) & 1);
-        const bool more = ch + 1 < a.ch1;
-        if (more) pair_load<F>(a, m0, n0, ch + 1, stage);
-
-        v4i fa[8], fb[8];
-#pragma unroll
-        for (int s = 0; s < 8; ++s) {
-            fa[s] = __builtin_bit_cast(v4i, sA[cur][a_off + 2 * s]);
-            fb[s] = __builtin_bit_cast(v4i, sB[cur][b_off + 2 * s]);
-        }
-#pragma unroll
-        for (int lv = 0; lv < 8; ++lv)
-#pragma unroll
-            for (int s = 0; s <= lv; ++s)
-                acc[lv] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[s], fb[lv - s], acc[lv], 0, 0, 0);
-
-        if (more) pair_store<F>(sA[cur ^ 1], sB[cur ^ 1], stage);
-        __syncthreads();
-    }
-
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        double hi = (double)acc[0][r] * 0x1p21;
-        hi = hi + (double)acc[1][r] * 0x1p14;
-        hi = hi + (double)acc[2][r] * 0x1p7;
-        hi = hi + (double)acc[3][r];
-        double lo = (double)acc[4][r] * 0x1p21;
-        lo = lo + (double)acc[5][r] * 0x1p14;
-        lo = lo + (double)acc[6][r] * 0x1p7;
-        lo = lo + (double)acc[7][r];
-        const double v = fma(hi, 0x1p-35, lo * 0x1p-63);
-        store_c(a, m0 + wm * 32 + acc_row(lane, r), n0 + wn * 32 + r32, v);
-    }
-}
-
 // int8, pipelined: one wave per SIMD (4 waves as 2 x 2), each wave a 64 x 32
 // block of C held as two 32x32 accumulators per level (256 accumulator
 // registers).  Three LDS stages are filled by direct global->LDS loads (no

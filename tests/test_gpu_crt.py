@@ -175,3 +175,20 @@ def test_full_size_sampled_rows(dev, orc):
     # the oracle run on the sampled rows of A with the whole of B is the same product
     want = orc.crt_gemm(1.0, A[rows], B, nthreads=orc.num_procs())
     assert_bitwise(got, want, "n=8192 rows")
+
+
+def test_extreme_exponents(dev, orc):
+    """Products that underflow to subnormals and overflow to infinity: the single
+    rounding and the power-of-two scaling follow the oracle bit for bit (the GPU
+    keeps FP64 subnormals)."""
+    m, n, k = 37, 45, 29
+    say("crt extreme exponents")
+    base_a = synth.uniform_pm1((m, k), 51)
+    base_b = synth.uniform_pm1((k, n), 52)
+    for ea, eb in ((-1000, -60), (-520, -500), (-1040, -20), (600, 423), (1000, 22)):
+        A = np.ldexp(base_a, ea)
+        B = np.ldexp(base_b, eb)
+        got = gpu_crt(dev, A, B, np.zeros((m, n)), 1.0, 0.0)
+        with np.errstate(over="ignore"):
+            want = orc.crt_gemm(1.0, A, B)
+        assert_bitwise(got, want, (ea, eb))

@@ -173,3 +173,22 @@ def test_full_size_4096_sampled_rows(dev, orc, dtype):
     say(f"  oracle split model on {len(rows)} rows")
     want = orc.split_gemm(1.0, A[rows], B, fmt=fmt, S=S, nthreads=orc.num_procs())
     assert np.array_equal(got[rows], want)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_extreme_exponents(dev, orc, dtype):
+    """Products that underflow to subnormals or overflow: the one rounding of the
+    exact level sum and the power-of-two scaling follow the oracle bit for bit."""
+    fmt, S = FMT[dtype]
+    m, n, k = 37, 45, 29
+    base_a = synth.uniform_pm1((m, k), 51)
+    base_b = synth.uniform_pm1((k, n), 52)
+    for ea, eb in ((-1000, -60), (-520, -500), (-1040, -20), (600, 423), (1000, 22)):
+        say(f"split {mg.DTYPE_NAMES[dtype]} exponents {(ea, eb)}")
+        A = np.ldexp(base_a, ea)
+        B = np.ldexp(base_b, eb)
+        got = gpu_split(dev, A, B, np.zeros((m, n)), 1.0, 0.0, dtype)
+        with np.errstate(over="ignore"):
+            want = orc.split_gemm(1.0, A, B, fmt=fmt, S=S)
+        bad = np.argwhere(got != want)
+        assert bad.size == 0, (ea, eb, bad[:5], got[tuple(bad[0])], want[tuple(bad[0])])
