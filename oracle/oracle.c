@@ -2,7 +2,7 @@
  * Oracle for the tiled GEMM C = alpha*A*B + beta*C -- TEST INFRASTRUCTURE ONLY.
  *
  * Plain, slow, obviously correct CPU code that the tests, the smoke check and the
- * benchmark's CPU-baseline leg use to judge the GPU library.  It shares no code,
+ * benchmark's CPU-baseline leg use to check the GPU library.  It shares no code,
  * header, table or helper with the GPU path, and the product never calls it.
  *
  * Built with  gcc -O2 -mavx2 -mfma -ffp-contract=off -fopenmp  : no product a*b+c
@@ -22,7 +22,7 @@
  *   orc_gemm_dot2   -- the same result computed with a double-double accumulator
  *                      (Ogita, Rump, Oishi, "Accurate sum and dot product", SIAM J.
  *                      Sci. Comput. 26(6), 2005, algorithm Dot2): a reference whose
- *                      own error is about u^2, used to judge paths whose error is
+ *                      own error is about u^2, used to check paths whose error is
  *                      near the FP64 oracle's own.
  *   orc_split_*     -- the split-precision (Ozaki-style) emulation of an FP64 GEMM:
  *                      exact power-of-two scaling per row of A and column of B, exact

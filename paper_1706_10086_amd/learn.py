@@ -5,7 +5,7 @@ The paper tunes its two parameters by exhaustive search on two matrix sizes
 itself expensive (Sec. 6).  Here the tuner's sweep over many shapes trains a
 small network that predicts, for an unseen shape, the relative speed of every
 configuration; the configuration with the highest prediction is used, and the
-exhaustive sweep remains the fallback and the judge of the prediction's regret.
+exhaustive sweep remains the fallback and the measure of the prediction's regret.
 
 * features  x = [log2 m, log2 n, log2 k, onehot(F64, F32, split-BF16)], scaled
             by the training set's mean and standard deviation;

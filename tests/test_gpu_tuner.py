@@ -1,5 +1,5 @@
 """The learned configuration predictor on the GPU: the MLP is trained by the
-library's kernels on the shipped MI355X tuner database and judged on the 500
+library's kernels on the shipped MI355X tuner database and evaluated on the 500
 held-out shapes (FP64 and FP32) against the exhaustive best: geometric mean of
 TFLOP/s(predicted) / TFLOP/s(best) >= 0.95, and better than the method without
 the network (one tuned configuration per dtype)."""
