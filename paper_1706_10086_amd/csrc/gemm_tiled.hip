@@ -7,7 +7,7 @@
 // tile cache of Eq. 5, here (BM*BK + BK*BN) * S bytes per stage); an inner loop
 // multiplies the staged tiles into a per-thread register sub-tile of C (the
 // thread-local temporary C tile of Fig. 2, the multiply-add of Listing 2); C is
-// read and written once at the end (the "streaming" epilogue of Fig. 2).
+// read and written once at the end (the streamed epilogue of Fig. 2).
 //
 // gfx950 specifics (not from the paper):
 //  * the inner multiply runs on MFMA: v_mfma_f64_16x16x4_f64 for FP64 and
