@@ -180,9 +180,6 @@ template <bool SWZ> struct StageLayout {
     __device__ static int sw(int r) { return SWZ ? (r >> 2) & 3 : 0; }
 };
 
-// s_waitcnt immediate: vmcnt(n), no wait on the other counters
-constexpr int vmcnt_imm(int n) { return (n & 15) | ((n >> 4) << 14) | 0x70 | 0xF00; }
-
 struct CrtGemmArgs {
     const int8_t *QA;
     const int8_t *QB;

@@ -87,6 +87,9 @@ int crt_operand_bits(int64_t k);
 hipError_t crt_launch(const GemmArgs &g, hipStream_t s, const int *e, const int *fexp, int bits,
                       int8_t *QA, int8_t *QB, uint8_t *R, int64_t mp, int64_t np, int64_t kp);
 
+// s_waitcnt immediate for vmcnt(n) (n < 64), no wait on the other counters.
+constexpr int vmcnt_imm(int n) { return (n & 15) | ((n >> 4) << 14) | 0x70 | 0xF00; }
+
 // Number of work-groups a configuration launches for an m x n output.
 inline int64_t tiles_of(int64_t m, int64_t n, const mgemm_cfg &c) {
     return ((m + c.bm - 1) / c.bm) * ((n + c.bn - 1) / c.bn);

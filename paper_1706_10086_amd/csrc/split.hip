@@ -429,27 +429,33 @@ constexpr int Q_SROW = 17;                               // padded LDS row (unit
 constexpr int Q_STAGE = (Q_BM + Q_BN) * Q_SROW;          // 3264 units per stage
 constexpr int Q_LOADS = (Q_STAGE + 255) / 256;           // load instructions per wave
 
+// Load instruction i of chunk ch into stage (the last instruction only for the
+// waves whose units lie inside the stage).
+__device__ __attribute__((always_inline)) inline void q_issue_one(
+    const PairArgs &a, int i, uint32_t a_row0, uint32_t b_row0, uint32_t ch, u32x4 *stage,
+    int wave, int lane) {
+    const uint32_t run = 256u, stride = (uint32_t)a.nch * 256u;
+    const int first = i * 256 + wave * 64;            // first unit of this wave instruction
+    if (first >= Q_STAGE) return;                     // uniform per wave
+    const int u = first + lane;
+    const uint8_t *src;
+    if (u < Q_BM * Q_SROW) {
+        const int row = u / Q_SROW, c = u % Q_SROW;
+        src = a.QA + ((a_row0 + row) * stride + ch * run + (uint32_t)(c < Q_UNITS ? c : Q_UNITS - 1) * 16u);
+    } else {
+        const int v = u - Q_BM * Q_SROW;
+        const int row = v / Q_SROW, c = v % Q_SROW;
+        src = a.QB + ((b_row0 + row) * stride + ch * run + (uint32_t)(c < Q_UNITS ? c : Q_UNITS - 1) * 16u);
+    }
+    __builtin_amdgcn_global_load_lds(
+        (const void *)src, (__attribute__((address_space(3))) void *)(stage + first), 16, 0, 0);
+}
+
 __device__ __attribute__((always_inline)) inline void q_issue_loads(
     const PairArgs &a, uint32_t a_row0, uint32_t b_row0, uint32_t ch, u32x4 *stage, int wave,
     int lane) {
-    const uint32_t run = 256u, stride = (uint32_t)a.nch * 256u;
 #pragma unroll
-    for (int i = 0; i < Q_LOADS; ++i) {
-        const int first = i * 256 + wave * 64;        // first unit of this wave instruction
-        if (first >= Q_STAGE) continue;               // uniform per wave
-        const int u = first + lane;
-        const uint8_t *src;
-        if (u < Q_BM * Q_SROW) {
-            const int row = u / Q_SROW, c = u % Q_SROW;
-            src = a.QA + ((a_row0 + row) * stride + ch * run + (uint32_t)(c < Q_UNITS ? c : Q_UNITS - 1) * 16u);
-        } else {
-            const int v = u - Q_BM * Q_SROW;
-            const int row = v / Q_SROW, c = v % Q_SROW;
-            src = a.QB + ((b_row0 + row) * stride + ch * run + (uint32_t)(c < Q_UNITS ? c : Q_UNITS - 1) * 16u);
-        }
-        __builtin_amdgcn_global_load_lds(
-            (const void *)src, (__attribute__((address_space(3))) void *)(stage + first), 16, 0, 0);
-    }
+    for (int i = 0; i < Q_LOADS; ++i) q_issue_one(a, i, a_row0, b_row0, ch, stage, wave, lane);
 }
 
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
@@ -478,8 +484,10 @@ split_pairs_i8_pipe_kernel(PairArgs a) {
     const uint32_t ar0 = (uint32_t)m0, br0 = (uint32_t)n0;
     // products of the current chunk; every fragment is reloaded from the next
     // stage right after its last use (after the last chunk the reloads read a
-    // stale stage and are never used -- they stay inside the LDS allocation)
-    auto products = [&](const u32x4 *nst) {
+    // stale stage and are never used -- they stay inside the LDS allocation),
+    // and the loads of chunk lc into stage lst go out one every two slice pairs
+    auto products = [&](const u32x4 *nst, uint32_t lc, u32x4 *lst) {
+        int slot = 0;
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
 #pragma unroll
@@ -489,11 +497,12 @@ split_pairs_i8_pipe_kernel(PairArgs a) {
                     acc[s + t][mt] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[s][mt], fb[t],
                                                                             acc[s + t][mt], 0, 0, 0);
                 // fb[t] is last used by slice s = 7 - t; the scheduling barriers
-                // keep each reload next to the products it overlaps
-                if (t == 7 - s) {
-                    fb[t] = __builtin_bit_cast(v4i, nst[b_off + 2 * t]);
-                    __builtin_amdgcn_sched_barrier(0);
-                }
+                // keep each reload and load next to the products it overlaps
+                if (t == 7 - s) fb[t] = __builtin_bit_cast(v4i, nst[b_off + 2 * t]);
+                if (slot % 2 == 0 && slot / 2 < Q_LOADS)
+                    q_issue_one(a, slot / 2, ar0, br0, lc, lst, wave, lane);
+                ++slot;
+                __builtin_amdgcn_sched_barrier(0);
             }
             fa[s][0] = __builtin_bit_cast(v4i, nst[a_off0 + 2 * s]);
             fa[s][1] = __builtin_bit_cast(v4i, nst[a_off1 + 2 * s]);
@@ -503,7 +512,7 @@ split_pairs_i8_pipe_kernel(PairArgs a) {
 
     const uint32_t c0 = (uint32_t)a.ch0, c1 = (uint32_t)a.ch1;
     q_issue_loads(a, ar0, br0, c0, lds, wave, lane);
-    if (c0 + 1 < c1) q_issue_loads(a, ar0, br0, c0 + 1, lds + Q_STAGE, wave, lane);
+    q_issue_loads(a, ar0, br0, c0 + 1 < c1 ? c0 + 1 : c0, lds + Q_STAGE, wave, lane);
     __builtin_amdgcn_s_waitcnt(0x0F70);          // vmcnt(0)
     __syncthreads();
 #pragma unroll
@@ -519,10 +528,11 @@ split_pairs_i8_pipe_kernel(PairArgs a) {
         __syncthreads();
         const int st1 = st == 2 ? 0 : st + 1;
         const int st2 = st1 == 2 ? 0 : st1 + 1;
-        if (c + 2 < c1) q_issue_loads(a, ar0, br0, c + 2, lds + st2 * Q_STAGE, wave, lane);
-        products(lds + st1 * Q_STAGE);
+        // chunk c+2 (past the end: the last chunk again, in bounds, never used)
+        products(lds + st1 * Q_STAGE, c + 2 < c1 ? c + 2 : c1 - 1, lds + st2 * Q_STAGE);
         st = st1;
     }
+    __builtin_amdgcn_s_waitcnt(0x0F70);          // vmcnt(0): no load lands after this point
 
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt)
@@ -539,6 +549,150 @@ split_pairs_i8_pipe_kernel(PairArgs a) {
             const double v = fma(hi, 0x1p-35, lo * 0x1p-63);
             store_c(a, m0 + wm * 64 + mt * 32 + acc_row(lane, r), n0 + wn * 32 + r32, v);
         }
+}
+
+// bf16, pipelined: 8 waves (2 x 4, two per SIMD) own a 64 x 128 tile of C, each
+// wave a 32 x 32 block held as one 32x32 FP32 accumulator per level plus the
+// exact FP64 hi / lo sums.  Four LDS stages (one k-chunk of all 6 slices of the
+// tile's 64 A rows and 128 B columns each) are filled by direct global->LDS loads
+// three chunks ahead, spread over the products; fragments are refilled from the
+// next stage right after their last use.  Chunks run in blocks of 16, so each
+// level's flush into hi / lo (after 16, 8, 4, 4, 2, 2 chunks) is placed at compile
+// time; the pass's chunk range is a multiple of 16 (k padded with zero slices).
+constexpr int R_BM = 64, R_BN = 128;
+constexpr int R_THREADS = 512;
+constexpr int R_UNITS = 12;                              // units of one row run (6 x 32 B)
+constexpr int R_SROW = 13;                               // padded LDS row (units)
+constexpr int R_AUNITS = R_BM * R_SROW;                  // 832 units
+constexpr int R_STAGE = (R_BM + R_BN) * R_SROW;          // 2496 units per stage
+constexpr int R_LOADS = (R_STAGE + R_THREADS - 1) / R_THREADS;   // 5 load instructions per lane
+constexpr int R_NST = 4;
+constexpr int R_BLOCK = 16;                              // chunks per flush cycle
+static_assert(R_AUNITS % 64 == 0 && R_STAGE % 64 == 0, "a wave's loads lie in one operand");
+static_assert(R_NST * R_STAGE * 16 <= 163840, "LDS");
+
+__global__ void __launch_bounds__(R_THREADS) __attribute__((amdgpu_waves_per_eu(2)))
+split_pairs_bf16_pipe_kernel(PairArgs a) {
+    __shared__ u32x4 lds[R_NST * R_STAGE];
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = wave >> 2, wn = wave & 3;
+    int tm, tn;
+    tile_of_block(blockIdx.x, gridDim.x, a.tiles_m, a.tiles_n, tm, tn);
+    const int64_t m0 = (int64_t)tm * R_BM, n0 = (int64_t)tn * R_BN;
+    const int r32 = lane & 31, kh = lane >> 5;
+    const int a_off = (wm * 32 + r32) * R_SROW + kh;
+    const int b_off = R_AUNITS + (wn * 32 + r32) * R_SROW + kh;
+
+    // per-lane source offsets (bytes, chunk 0) of each load instruction; the
+    // slices of one row are nch runs of 192 bytes
+    const uint32_t stride = (uint32_t)a.nch * 192u;
+    uint32_t off[R_LOADS];
+#pragma unroll
+    for (int i = 0; i < R_LOADS; ++i) {
+        const int u = i * R_THREADS + wave * 64 + lane;
+        const int v = u < R_AUNITS ? u : u - R_AUNITS;
+        const int row = v / R_SROW, c = v % R_SROW;
+        const uint32_t row0 = u < R_AUNITS ? (uint32_t)m0 : (uint32_t)n0;
+        off[i] = (row0 + (uint32_t)row) * stride + (uint32_t)(c < R_UNITS ? c : R_UNITS - 1) * 16u;
+    }
+    // load instruction i of chunk ch into stage st (the last instruction only
+    // for the waves whose units lie inside the stage)
+    auto issue_one = [&](int i, uint32_t ch, int st) {
+        const int first = i * R_THREADS + wave * 64;             // uniform per wave
+        if ((i + 1) * R_THREADS > R_STAGE && first >= R_STAGE) return;
+        const uint8_t *src = (first < R_AUNITS ? a.QA : a.QB) + (off[i] + ch * 192u);
+        __builtin_amdgcn_global_load_lds((const void *)src,
+                                         (__attribute__((address_space(3))) void *)(lds + st * R_STAGE + first),
+                                         16, 0, 0);
+    };
+    // waves whose last instruction lies inside the stage issue R_LOADS loads per
+    // chunk, the others one fewer
+    const bool full_loads = (R_LOADS - 1) * R_THREADS + wave * 64 < R_STAGE;
+
+    v16f acc[6];
+#pragma unroll
+    for (int l = 0; l < 6; ++l) acc[l] = v16f{};
+    double hi[16], lo[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) hi[r] = lo[r] = 0.0;
+    v8bf fa[6], fb[6];
+
+    // products of one chunk (21 slice pairs); fragments are refilled from the
+    // next stage after their last use, and the loads of chunk lc into stage ls go
+    // out one every four slice pairs
+    auto products = [&](const u32x4 *nst, uint32_t lc, int ls) {
+        int slot = 0;
+#pragma unroll
+        for (int s = 0; s < 6; ++s) {
+#pragma unroll
+            for (int t = 5 - s; t >= 0; --t) {
+                acc[s + t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[s], fb[t], acc[s + t], 0, 0, 0);
+                if (t == 5 - s) fb[t] = __builtin_bit_cast(v8bf, nst[b_off + 2 * t]);
+                if (slot % 4 == 0 && slot / 4 < R_LOADS) issue_one(slot / 4, lc, ls);
+                ++slot;
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            fa[s] = __builtin_bit_cast(v8bf, nst[a_off + 2 * s]);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    };
+    // hi holds levels 2..4 (lv 0..2) in units of level 4, lo levels 5..7 (lv 3..5)
+    // in units of level 7: both stay exact integers
+    auto flush = [&](int lv) {
+        const double sc = (double)(1 << (9 * (2 - (lv % 3))));
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            if (lv < 3) hi[r] = fma((double)acc[lv][r], sc, hi[r]);
+            else lo[r] = fma((double)acc[lv][r], sc, lo[r]);
+        }
+        acc[lv] = v16f{};
+    };
+
+    const uint32_t c0 = (uint32_t)a.ch0;
+    const int nch = (int)(a.ch1 - a.ch0);         // a multiple of R_BLOCK
+    const uint32_t clast = c0 + (uint32_t)nch - 1;
+#pragma unroll
+    for (int c = 0; c < R_NST - 1; ++c) {
+        const uint32_t ch = c0 + (uint32_t)c <= clast ? c0 + (uint32_t)c : clast;
+#pragma unroll
+        for (int i = 0; i < R_LOADS; ++i) issue_one(i, ch, c);
+    }
+    // chunk 0 landed; two chunks' loads may remain
+    if (full_loads) __builtin_amdgcn_s_waitcnt(vmcnt_imm(2 * R_LOADS));
+    else __builtin_amdgcn_s_waitcnt(vmcnt_imm(2 * (R_LOADS - 1)));
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+        fa[s] = __builtin_bit_cast(v8bf, lds[a_off + 2 * s]);
+        fb[s] = __builtin_bit_cast(v8bf, lds[b_off + 2 * s]);
+    }
+    constexpr int PERIOD[6] = {16, 8, 4, 4, 2, 2};
+    for (int b = 0; b < nch; b += R_BLOCK) {
+#pragma unroll 1
+        for (int u = 0; u < R_BLOCK; ++u) {
+            // chunk c = b + u (stage u % 4): chunk c+1 landed, one chunk may remain
+            if (full_loads) __builtin_amdgcn_s_waitcnt(vmcnt_imm(R_LOADS));
+            else __builtin_amdgcn_s_waitcnt(vmcnt_imm(R_LOADS - 1));
+            __syncthreads();
+            const uint32_t next = c0 + (uint32_t)(b + u + 3);
+            // chunk c+3 into the stage of chunk c-1 (past the end: the last
+            // chunk again, in bounds and never used)
+            products(lds + ((u + 1) & 3) * R_STAGE, next <= clast ? next : clast, (u + 3) & 3);
+#pragma unroll
+            for (int lv = 0; lv < 6; ++lv)
+                if ((u + 1) % PERIOD[lv] == 0) flush(lv);
+        }
+    }
+    __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));     // no load lands after this point
+
+    // exact value = hi 2^-34 + lo 2^-61, rounded once
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const double v = fma(hi[r], 0x1p-34, lo[r] * 0x1p-61);
+        store_c(a, m0 + wm * 32 + acc_row(lane, r), n0 + wn * 32 + r32, v);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -587,6 +741,8 @@ static inline int64_t round_up(int64_t x, int64_t q) { return (x + q - 1) / q * 
 struct PairKernel {
     void (*fn)(PairArgs);
     int tile_m, tile_n, threads;
+    int kpad;         // k padded to a multiple of this (a multiple of KPAD)
+    int chunk_mult;   // each pass covers a multiple of this many chunks
 };
 
 constexpr int64_t SPLIT_PAD = 128;   // m and n padded to a multiple of every pair tile
@@ -595,7 +751,7 @@ template <typename F>
 static int32_t run_split(const GemmArgs &g, hipStream_t s, Workspace &w, int max_pass_k,
                          PairKernel pk) {
     const int64_t mp = round_up(g.m, SPLIT_PAD), np = round_up(g.n, SPLIT_PAD),
-                  kp = round_up(g.k, KPAD);
+                  kp = round_up(g.k, pk.kpad);
     const size_t a_bytes = (size_t)mp * kp * F::S * F::ELEM;
     const size_t b_bytes = (size_t)np * kp * F::S * F::ELEM;
     const size_t e_bytes = round_up(mp * 4, 256), f_bytes = round_up(np * 4, 256);
@@ -651,7 +807,8 @@ static int32_t run_split(const GemmArgs &g, hipStream_t s, Workspace &w, int max
     pa.tiles_n = (int)(np / pk.tile_n);
     const int64_t blocks = (int64_t)pa.tiles_m * pa.tiles_n;
     const int64_t pass_ch = max_pass_k / F::KC;
-    const int64_t kch = (g.k + F::KC - 1) / F::KC;   // chunks holding data
+    // chunks holding data, rounded up to the kernel's multiple (zero slices)
+    const int64_t kch = round_up((g.k + F::KC - 1) / F::KC, pk.chunk_mult);
     for (int64_t c0 = 0; c0 < kch; c0 += pass_ch) {
         pa.ch0 = c0;
         pa.ch1 = c0 + pass_ch < kch ? c0 + pass_ch : kch;
@@ -713,8 +870,18 @@ int32_t split_gemm(const GemmArgs &g, int32_t dtype, hipStream_t s) {
         return set_error(MGEMM_ERR_HIP, "split: no current device");
     Workspace &w = g_ws[dev];
     std::lock_guard<std::mutex> lock(w.mtx);
-    if (dtype == MGEMM_SPLIT_BF16)
-        return run_split<FmtBF16>(g, s, w, 1 << 17, PairKernel{split_pairs_bf16_kernel, PBM, PBN, 512});
+    if (dtype == MGEMM_SPLIT_BF16) {
+        // the pipelined kernel addresses each operand's slices with 32-bit offsets;
+        // larger operands take the register-staged kernel (64-bit addresses)
+        const double big = (double)round_up(g.m > g.n ? g.m : g.n, SPLIT_PAD) *
+                           (double)round_up(g.k, 256) * FmtBF16::S * FmtBF16::ELEM;
+        if (big < 4294967296.0)
+            return run_split<FmtBF16>(g, s, w, 1 << 17,
+                                      PairKernel{split_pairs_bf16_pipe_kernel, R_BM, R_BN, R_THREADS,
+                                                 256, R_BLOCK});
+        return run_split<FmtBF16>(g, s, w, 1 << 17,
+                                  PairKernel{split_pairs_bf16_kernel, PBM, PBN, 512, KPAD, 1});
+    }
     if (dtype == MGEMM_SPLIT_INT8) {
         // the pipelined kernel addresses each operand's slices with 32-bit offsets
         const double big = (double)round_up(g.m > g.n ? g.m : g.n, SPLIT_PAD) *
@@ -722,7 +889,7 @@ int32_t split_gemm(const GemmArgs &g, int32_t dtype, hipStream_t s) {
         if (big >= 4294967296.0)
             return set_error(MGEMM_ERR_NOCONFIG, "split int8: slices of one operand exceed 4 GiB");
         return run_split<FmtI8>(g, s, w, 1 << 14,
-                                PairKernel{split_pairs_i8_pipe_kernel, Q_BM, Q_BN, 256});
+                                PairKernel{split_pairs_i8_pipe_kernel, Q_BM, Q_BN, 256, KPAD, 1});
     }
     if (dtype == MGEMM_CRT_INT8) return run_crt(g, s, w);
     return set_error(MGEMM_ERR_NOCONFIG, "split dtype %d is not built", dtype);
