@@ -55,7 +55,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extras", action="store_true", help="only the FP64 headline leg")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--leg", choices=["parity", "sweep", "split", "batched", "tuner"], default=None,
+    ap.add_argument("--leg", choices=["parity", "sweep", "split", "batched", "batched_plan", "tuner"],
+                    default=None,
                     help="run only this extra leg and print its JSON (for profiling runs)")
     return ap.parse_args()
 
@@ -218,27 +219,40 @@ def leg_sweep(mg, torch, dev, sizes=(1024, 2048, 4096, 8192, 16384)):
     return out
 
 
-def leg_batched(mg, torch, dev):
+def leg_batched(mg, torch, dev, plan_only=False):
+    """The batched workload: FP64 and FP32 plans, each against per-problem launches
+    and (FP64) the oracle.  plan_only: the plan executions alone (a profiling run
+    with few dispatches)."""
     import synth
     log("bench: batched leg, 2048 uneven FP64 problems")
     cnt = 2048
     ms = synth.log_uniform_int(cnt, 4001, 16, 1024)
     ns = synth.log_uniform_int(cnt, 4002, 16, 1024)
     ks = synth.log_uniform_int(cnt, 4003, 16, 1024)
+    # every operand is a view into one buffer (each starting on a 512-byte
+    # boundary, as a separate allocation would): one fill instead of thousands;
+    # beta = 0, so C's initial values are never read
+    sizes = [int(s) for m, n, k in zip(ms, ns, ks) for s in (m * k, k * n, m * n)]
+    offs = np.concatenate([[0], np.cumsum([(s + 63) // 64 * 64 for s in sizes])])
     g = torch.Generator(device=dev)
     g.manual_seed(4004)
-    As = [torch.rand((int(m), int(k)), device=dev, dtype=torch.float64, generator=g) * 2 - 1
-          for m, k in zip(ms, ks)]
-    Bs = [torch.rand((int(k), int(n)), device=dev, dtype=torch.float64, generator=g) * 2 - 1
-          for k, n in zip(ks, ns)]
-    Cs = [torch.zeros((int(m), int(n)), device=dev, dtype=torch.float64) for m, n in zip(ms, ns)]
+    buf = torch.rand(int(offs[-1]), device=dev, dtype=torch.float64, generator=g) * 2 - 1
+    views = [buf[int(offs[i]):int(offs[i]) + sizes[i]] for i in range(len(sizes))]
+    As = [views[3 * i].view(int(m), int(k)) for i, (m, k) in enumerate(zip(ms, ks))]
+    Bs = [views[3 * i + 1].view(int(k), int(n)) for i, (k, n) in enumerate(zip(ks, ns))]
+    Cs = [views[3 * i + 2].view(int(m), int(n)) for i, (m, n) in enumerate(zip(ms, ns))]
     flops = float(sum(2.0 * m * n * k for m, n, k in zip(ms, ns, ks)))
     stream = torch.cuda.current_stream()
     plan = mg.BatchedPlan(As, Bs, Cs, 1.0, 0.0, stream=stream)
     tp = timed(plan.execute, stream, 10, warmup=2)
-    tl = timed(lambda: mg.gemm_batched(As, Bs, Cs, 1.0, 0.0), stream, 3, warmup=1)
+    log("bench: FP64 plan timed")
     info = plan.info()
     plan.destroy()
+    if plan_only:
+        tl = [float("nan")]
+    else:
+        tl = timed(lambda: mg.gemm_batched(As, Bs, Cs, 1.0, 0.0), stream, 3, warmup=1)
+        log("bench: FP64 per-problem launches timed")
     nbytes = float(sum(8.0 * (m * k + k * n + m * n) for m, n, k in zip(ms, ns, ks)))
     gms = float(np.mean(tp))
     out = {"problems": cnt, "flops": flops, "bytes": nbytes, "buckets": info["buckets"],
@@ -246,35 +260,43 @@ def leg_batched(mg, torch, dev):
            "graph_tflops": round(flops / gms / 1e9, 3),
            # max(sum F / peak, sum B / bandwidth) / t: the batch's roofline fraction
            "roofline_frac": round(max(flops / (PEAK_F64_TFLOPS * 1e12), nbytes / 8e12) / (gms * 1e-3), 4),
-           "per_problem_ms": round(float(np.mean(tl)), 4),
-           "per_problem_tflops": round(flops / float(np.mean(tl)) / 1e9, 3),
-           "speedup": round(float(np.mean(tl)) / gms, 3)}
-    # the oracle on every problem of the batch, all host cores (the first 512
-    # problems, scaled by FLOP to the whole batch)
-    import oracle
-    sub = 512
-    t = time.perf_counter()
-    for i in range(sub):
-        oracle.gemm_f64(1.0, As[i].cpu().numpy(), Bs[i].cpu().numpy(), 0.0, None,
-                        nthreads=oracle.num_procs())
-    t_sub = time.perf_counter() - t
-    f_sub = float(sum(2.0 * m * n * k for m, n, k in zip(ms[:sub], ns[:sub], ks[:sub])))
-    out["oracle_batch_s_estimate"] = round(t_sub * flops / f_sub, 2)
+           "per_problem_ms": None if plan_only else round(float(np.mean(tl)), 4),
+           "per_problem_tflops": None if plan_only else round(flops / float(np.mean(tl)) / 1e9, 3),
+           "speedup": None if plan_only else round(float(np.mean(tl)) / gms, 3)}
+    if not plan_only:
+        # the oracle on every problem of the batch, all host cores (the first 512
+        # problems, scaled by FLOP to the whole batch)
+        import oracle
+        sub = 512
+        t = time.perf_counter()
+        for i in range(sub):
+            oracle.gemm_f64(1.0, As[i].cpu().numpy(), Bs[i].cpu().numpy(), 0.0, None,
+                            nthreads=oracle.num_procs())
+        t_sub = time.perf_counter() - t
+        f_sub = float(sum(2.0 * m * n * k for m, n, k in zip(ms[:sub], ns[:sub], ks[:sub])))
+        out["oracle_batch_s_estimate"] = round(t_sub * flops / f_sub, 2)
     # FP32 variant of the same batch
-    As32 = [a.float() for a in As]
-    Bs32 = [b.float() for b in Bs]
-    Cs32 = [c.float() for c in Cs]
-    del As, Bs, Cs
+    buf32 = buf.float()
+    del As, Bs, Cs, views, buf
+    views = [buf32[int(offs[i]):int(offs[i]) + sizes[i]] for i in range(len(sizes))]
+    As32 = [views[3 * i].view(int(m), int(k)) for i, (m, k) in enumerate(zip(ms, ks))]
+    Bs32 = [views[3 * i + 1].view(int(k), int(n)) for i, (k, n) in enumerate(zip(ks, ns))]
+    Cs32 = [views[3 * i + 2].view(int(m), int(n)) for i, (m, n) in enumerate(zip(ms, ns))]
     plan = mg.BatchedPlan(As32, Bs32, Cs32, 1.0, 0.0, stream=stream)
     tp = timed(plan.execute, stream, 10, warmup=2)
-    tl = timed(lambda: mg.gemm_batched(As32, Bs32, Cs32, 1.0, 0.0), stream, 3, warmup=1)
+    log("bench: FP32 plan timed")
     plan.destroy()
+    if plan_only:
+        tl = [float("nan")]
+    else:
+        tl = timed(lambda: mg.gemm_batched(As32, Bs32, Cs32, 1.0, 0.0), stream, 3, warmup=1)
+        log("bench: FP32 per-problem launches timed")
     g32 = float(np.mean(tp))
     out["f32"] = {"graph_ms": round(g32, 4), "graph_tflops": round(flops / g32 / 1e9, 3),
                   "roofline_frac": round(max(flops / (PEAK_F32_TFLOPS * 1e12), nbytes / 2 / 8e12) /
                                          (g32 * 1e-3), 4),
-                  "per_problem_ms": round(float(np.mean(tl)), 4),
-                  "speedup": round(float(np.mean(tl)) / g32, 3)}
+                  "per_problem_ms": None if plan_only else round(float(np.mean(tl)), 4),
+                  "speedup": None if plan_only else round(float(np.mean(tl)) / g32, 3)}
     return out
 
 
@@ -354,6 +376,7 @@ def main():
                 "sweep": lambda: leg_sweep(mg, torch, dev),
                 "parity": lambda: leg_parity(mg, torch, dev),
                 "batched": lambda: leg_batched(mg, torch, dev),
+                "batched_plan": lambda: leg_batched(mg, torch, dev, plan_only=True),
                 "tuner": lambda: leg_tuner(mg)}
         print(json.dumps({args.leg: legs[args.leg]()}), flush=True)
         return 0

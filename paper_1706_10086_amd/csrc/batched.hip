@@ -3,18 +3,19 @@
 //  * gemm_batched            one gemm_ex launch per problem (the per-problem
 //                            baseline).
 //  * gemm_batched_plan_*     problems are grouped by tile configuration (chosen
-//                            per problem, or given by the caller) and by row
-//                            alignment into buckets; each bucket's problems are
-//                            ordered by decreasing work and numbered tile by tile
-//                            into one work list, copied to the device once; one
-//                            persistent kernel per bucket (grid = resident
-//                            work-groups of the whole GPU) pulls tiles from an
-//                            atomic counter.  A counter-reset kernel and the
-//                            bucket kernels (as parallel branches) are captured
-//                            once into a HIP graph; executing the plan is one
-//                            hipGraphLaunch.  Each tile runs the same code as
-//                            gemm_ex with the same configuration, so results are
-//                            bitwise identical to per-problem gemm_ex calls.
+//                            per problem, or given by the caller) into buckets;
+//                            each bucket's problems are ordered by decreasing
+//                            work and dealt into work lists (one per XCD; a map
+//                            entry names a problem, tile row and tile column),
+//                            copied to the device once; one persistent kernel
+//                            per bucket (grid = resident work-groups of the whole
+//                            GPU) pulls tiles from atomic counters.  A
+//                            counter-reset kernel and the bucket kernels (as
+//                            parallel branches) are captured once into a HIP
+//                            graph; executing the plan is one hipGraphLaunch.
+//                            Each tile runs the same code as gemm_ex with the
+//                            same configuration and row alignment, so results
+//                            are bitwise identical to per-problem gemm_ex calls.
 #include <algorithm>
 #include <map>
 #include <vector>
@@ -39,12 +40,54 @@ __global__ void reset_counters_kernel(unsigned long long *c, int n) {
 
 struct Bucket {
     const KernelEntry *entry;
-    int align;                        // 0: aligned rows, 1: any rows
     std::vector<BatchProblem> probs;
     int64_t total_tiles = 0;
     int grid = 0;
     size_t offset = 0;                // byte offset of the descriptors in dev
+    size_t map_offset = 0;            // byte offset of the tile map in dev (if use_map)
+    size_t list_offset = 0;           // byte offset of the list bounds in dev
+    bool use_map = false;
+    std::vector<uint64_t> map;        // the lists' entries, list after list (host copy)
+    std::vector<int64_t> list_off;    // list l holds [list_off[l], list_off[l+1])
 };
+
+// Tile maps are built while every bucket's map fits this many bytes in total and
+// each entry's fields fit their bit widths; otherwise the kernels search.
+constexpr size_t TILE_MAP_MAX_BYTES = (size_t)256 << 20;
+
+// One list per XCD: problems, in decreasing work, are cut into runs of whole
+// tile rows of about 1/16 of a list's share of the work, and each run goes to the
+// list with the least work so far; a run's tiles share their rows of A (and read
+// the same B) in the L2 of the XCD that serves the list.
+static void build_lists(Bucket &b) {
+    const mgemm_cfg &c = b.entry->cfg;
+    double total = 0.0;
+    for (const BatchProblem &bp : b.probs)
+        total += (double)((bp.g.m + c.bm - 1) / c.bm) * (double)bp.tiles_n * (double)bp.g.k;
+    const double piece = std::max(total / (BATCH_LISTS * 16.0), 1.0);
+    std::vector<std::vector<uint64_t>> lists(BATCH_LISTS);
+    std::vector<double> load(BATCH_LISTS, 0.0);
+    for (size_t j = 0; j < b.probs.size(); ++j) {
+        const BatchProblem &bp = b.probs[j];
+        const int64_t tiles_m = (bp.g.m + c.bm - 1) / c.bm;
+        const double row_work = (double)bp.tiles_n * (double)bp.g.k;
+        const int64_t rows = std::max<int64_t>(1, (int64_t)(piece / row_work));
+        for (int64_t tm0 = 0; tm0 < tiles_m; tm0 += rows) {
+            const int64_t tm1 = std::min(tiles_m, tm0 + rows);
+            const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+            for (int64_t tm = tm0; tm < tm1; ++tm)
+                for (int64_t tn = 0; tn < bp.tiles_n; ++tn)
+                    lists[l].push_back(tile_map_entry(j, (uint64_t)tm, (uint64_t)tn));
+            load[l] += (double)(tm1 - tm0) * row_work;
+        }
+    }
+    b.map.clear();
+    b.list_off.assign(1, 0);
+    for (const auto &li : lists) {
+        b.map.insert(b.map.end(), li.begin(), li.end());
+        b.list_off.push_back((int64_t)b.map.size());
+    }
+}
 
 struct Plan {
     int device = 0;
@@ -131,8 +174,8 @@ int32_t gemm_batched_plan_create(int64_t count, const int64_t *m, const int64_t 
     p->count = count;
     hipGetDevice(&p->device);
 
-    // bucket by (configuration, alignment)
-    std::map<std::pair<const KernelEntry *, int>, size_t> index;
+    // bucket by configuration
+    std::map<const KernelEntry *, size_t> index;
     for (int64_t i = 0; i < count; ++i) {
         if (m[i] == 0 || n[i] == 0) continue;
         if (k[i] == 0 || alpha[i] == 0.0) {
@@ -153,21 +196,19 @@ int32_t gemm_batched_plan_create(int64_t count, const int64_t *m, const int64_t 
             return err ? err : set_error(MGEMM_ERR_NOCONFIG, "problem %lld: no configuration",
                                          (long long)i);
         }
-        const int al = rows_aligned(A[i], lda[i], B[i], ldb[i], dtype) ? 0 : 1;
-        auto key = std::make_pair(e, al);
-        auto it = index.find(key);
+        auto it = index.find(e);
         if (it == index.end()) {
-            index[key] = p->buckets.size();
+            index[e] = p->buckets.size();
             Bucket b;
             b.entry = e;
-            b.align = al;
             p->buckets.push_back(b);
-            it = index.find(key);
+            it = index.find(e);
         }
         BatchProblem bp;
         bp.g = GemmArgs{m[i], n[i], k[i], alpha[i], beta[i], A[i], lda[i], B[i], ldb[i], C[i], ldc[i]};
         bp.tile0 = 0;
         bp.tiles_n = (n[i] + e->cfg.bn - 1) / e->cfg.bn;
+        bp.aligned = rows_aligned(A[i], lda[i], B[i], ldb[i], dtype) ? 1 : 0;
         p->buckets[it->second].probs.push_back(bp);
         p->flops += 2.0 * (double)m[i] * (double)n[i] * (double)k[i];
     }
@@ -190,14 +231,43 @@ int32_t gemm_batched_plan_create(int64_t count, const int64_t *m, const int64_t 
             t += ((bp.g.m + c.bm - 1) / c.bm) * bp.tiles_n;
         }
         b.total_tiles = t;
-        const int64_t resident = (int64_t)cus * b.entry->batched_occupancy[b.align]();
+        const int64_t resident = (int64_t)cus * b.entry->batched_occupancy();
         b.grid = (int)std::min<int64_t>(resident, t);
         b.offset = bytes;
         bytes += (b.probs.size() * sizeof(BatchProblem) + 255) / 256 * 256;
     }
+    // tile maps (one 8-byte entry per tile, in per-XCD lists) if the fields fit
+    // and the total is modest; otherwise one list of tile numbers
+    {
+        bool fits = true;
+        size_t map_bytes = 0;
+        for (const Bucket &b : p->buckets) {
+            if (b.probs.size() >= ((size_t)1 << TILE_MAP_PROB_BITS)) fits = false;
+            for (const BatchProblem &bp : b.probs) {
+                const int64_t tiles_m = (bp.g.m + b.entry->cfg.bm - 1) / b.entry->cfg.bm;
+                if (tiles_m >= ((int64_t)1 << TILE_MAP_RC_BITS) ||
+                    bp.tiles_n >= ((int64_t)1 << TILE_MAP_RC_BITS))
+                    fits = false;
+            }
+            map_bytes += ((size_t)b.total_tiles * sizeof(uint64_t) + 255) / 256 * 256;
+        }
+        for (Bucket &b : p->buckets) {
+            if (fits && map_bytes <= TILE_MAP_MAX_BYTES) {
+                b.use_map = true;
+                build_lists(b);
+                b.map_offset = bytes;
+                bytes += (b.map.size() * sizeof(uint64_t) + 255) / 256 * 256;
+            } else {
+                b.list_off = {0, b.total_tiles};
+            }
+            b.list_offset = bytes;
+            bytes += (b.list_off.size() * sizeof(int64_t) + 255) / 256 * 256;
+        }
+    }
     const size_t counters_off = bytes;
     const int nb = (int)p->buckets.size();
-    bytes += (size_t)std::max(nb, 1) * sizeof(unsigned long long);
+    const int ncounters = std::max(nb, 1) * BATCH_LISTS;
+    bytes += (size_t)ncounters * sizeof(unsigned long long);
 
     hipError_t he = hipMalloc((void **)&p->dev, bytes);
     if (he != hipSuccess) {
@@ -209,6 +279,13 @@ int32_t gemm_batched_plan_create(int64_t count, const int64_t *m, const int64_t 
     for (Bucket &b : p->buckets) {
         he = hipMemcpy(p->dev + b.offset, b.probs.data(), b.probs.size() * sizeof(BatchProblem),
                        hipMemcpyHostToDevice);
+        if (he == hipSuccess && b.use_map)
+            he = hipMemcpy(p->dev + b.map_offset, b.map.data(), b.map.size() * sizeof(uint64_t),
+                           hipMemcpyHostToDevice);
+        if (he == hipSuccess)
+            he = hipMemcpy(p->dev + b.list_offset, b.list_off.data(),
+                           b.list_off.size() * sizeof(int64_t), hipMemcpyHostToDevice);
+        std::vector<uint64_t>().swap(b.map);
         if (he != hipSuccess) {
             plan_free(p);
             return hip_fail(he, "plan: descriptor copy");
@@ -230,15 +307,17 @@ int32_t gemm_batched_plan_create(int64_t count, const int64_t *m, const int64_t 
     }
     if (he == hipSuccess) he = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (he == hipSuccess) {
-        hipLaunchKernelGGL(reset_counters_kernel, dim3((unsigned)((std::max(nb, 1) + 63) / 64)),
-                           dim3(64), 0, cs, counters, std::max(nb, 1));
+        hipLaunchKernelGGL(reset_counters_kernel, dim3((unsigned)((ncounters + 63) / 64)),
+                           dim3(64), 0, cs, counters, ncounters);
         hipEventRecord(start, cs);
         for (int b = 0; b < nb; ++b) {
             Bucket &bk = p->buckets[b];
             hipStreamWaitEvent(branch[b], start, 0);
-            hipError_t le = bk.entry->batched[bk.align](
-                (const BatchProblem *)(p->dev + bk.offset), (int)bk.probs.size(), bk.total_tiles,
-                counters + b, bk.grid, branch[b]);
+            hipError_t le = bk.entry->batched(
+                (const BatchProblem *)(p->dev + bk.offset),
+                bk.use_map ? (const uint64_t *)(p->dev + bk.map_offset) : nullptr,
+                (const int64_t *)(p->dev + bk.list_offset), (int)bk.list_off.size() - 1,
+                (int)bk.probs.size(), counters + (size_t)b * BATCH_LISTS, bk.grid, branch[b]);
             if (le != hipSuccess && rc == 0) rc = hip_fail(le, "plan: bucket launch");
             hipEventRecord(done[b], branch[b]);
             hipStreamWaitEvent(cs, done[b], 0);

@@ -330,50 +330,110 @@ gemm_tiled_kernel(GemmArgs p) {
 }
 
 // Many GEMMs sharing one configuration: a persistent grid whose work-groups take
-// tile numbers from an atomic counter until the work list is exhausted.  Tiles
-// are numbered problem by problem (BatchProblem::tile0 is the first number of a
-// problem; the problems are ordered by decreasing work), and the problem of a
-// tile is found by binary search.  Every work-group leaves the loop once the
-// counter passes the total.
-template <typename T, int BM, int BN, int BK, int WGM, int WGN, int EPT, int DBUF, int OCC,
-          bool ALIGN>
+// work items from atomic counters until every list is exhausted.  With a tile
+// map (item = map entry: problem, tile row, tile column) there is one list per
+// XCD, each holding whole problems or runs of a problem's tiles, so the panels of
+// A and B that a run of tiles shares stay in that XCD's L2; a work-group drains
+// its own XCD's list, then takes from the others.  Without a map the single list
+// holds tile numbers (problems numbered tile by tile, BatchProblem::tile0 the
+// first of each) and a tile's problem is found by binary search.  Lists order
+// their problems by decreasing work.  Thread 0 asks for the next item as the
+// work-group starts a tile, so the atomic's latency hides behind the tile's work.
+// Waves per SIMD the batched kernel is compiled for: the configuration's
+// occupancy if it names one; for the four-wave 64 x 64 x 16 tile three (it
+// still fits without spilling, and a batch of short tiles is bound by load
+// latency, which more resident work-groups hide).
+constexpr int batched_waves(int bm, int bn, int bk, int waves, int occ) {
+    return occ > 0 ? occ : (bm * bn <= 64 * 64 && bk <= 16 && waves == 4 ? 3 : 1);
+}
+
+template <typename T, int BM, int BN, int BK, int WGM, int WGN, int EPT, int DBUF, int OCC>
 __global__ void __launch_bounds__(64 * WGM * WGN)
-__attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1)))
-gemm_batched_kernel(const BatchProblem *__restrict__ probs, int nprob, int64_t total_tiles,
-                    unsigned long long *counter) {
+__attribute__((amdgpu_waves_per_eu(batched_waves(BM, BN, BK, WGM * WGN, OCC))))
+gemm_batched_kernel(const BatchProblem *__restrict__ probs, const uint64_t *__restrict__ tile_map,
+                    const int64_t *__restrict__ list_off, int nlist, int nprob,
+                    unsigned long long *counters) {
     typedef TileLds<T, BM, BN, BK, DBUF> L;
     __shared__ __attribute__((aligned(16))) T sA[L::A_ELEMS];
     __shared__ __attribute__((aligned(16))) T sB[L::B_ELEMS];
     __shared__ int64_t next;
-    for (;;) {
-        if (threadIdx.x == 0) next = (int64_t)atomicAdd(counter, 1ull);
-        __syncthreads();
-        // the tile number is uniform: keep it (and all that follows from it) in
-        // scalar registers
+    // the item index is uniform: keep it (and all that follows from it) in
+    // scalar registers
+    auto uniform_next = [&]() {
         const uint64_t tv = (uint64_t)next;
-        const int64_t t = (int64_t)(((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(tv >> 32))
-                                     << 32) |
-                                    (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)tv));
-        __syncthreads();
-        if (t >= total_tiles) break;
-        int lo = 0, hi = nprob - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (probs[mid].tile0 <= t) lo = mid;
-            else hi = mid - 1;
+        return (int64_t)(((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(tv >> 32)) << 32) |
+                         (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)tv));
+    };
+    // thread 0's state: lists visited so far and the counter value last taken
+    const int home = (int)(blockIdx.x % (unsigned)nlist);
+    int visit = 0;
+    unsigned long long taken = 0;
+    // (thread 0) the item that `taken` names, moving on to the next list while
+    // the current one is exhausted; -1 once every list is
+    auto settle = [&]() -> int64_t {
+        for (;;) {
+            const int l = home + visit < nlist ? home + visit : home + visit - nlist;
+            const int64_t idx = list_off[l] + (int64_t)taken;
+            if (idx < list_off[l + 1]) return idx;
+            if (++visit >= nlist) return -1;
+            const int l2 = home + visit < nlist ? home + visit : home + visit - nlist;
+            taken = atomicAdd(&counters[l2], 1ull);
+        }
+    };
+    if (threadIdx.x == 0) {
+        taken = atomicAdd(&counters[home], 1ull);
+        next = settle();
+    }
+    __syncthreads();
+    int64_t t = uniform_next();
+    while (t >= 0) {
+        if (threadIdx.x == 0) {
+            const int l = home + visit < nlist ? home + visit : home + visit - nlist;
+            taken = atomicAdd(&counters[l], 1ull);                // read after this tile
+        }
+        int pi;
+        int64_t tm, tn;
+        if (tile_map) {
+            const uint64_t e = tile_map[t];
+            const uint64_t eu = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(e >> 32)) << 32) |
+                                (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)e);
+            constexpr uint64_t RC = (1ull << TILE_MAP_RC_BITS) - 1;
+            pi = (int)(eu >> (2 * TILE_MAP_RC_BITS));
+            tm = (int64_t)((eu >> TILE_MAP_RC_BITS) & RC);
+            tn = (int64_t)(eu & RC);
+        } else {
+            int lo = 0, hi = nprob - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (probs[mid].tile0 <= t) lo = mid;
+                else hi = mid - 1;
+            }
+            pi = lo;
+            tm = tn = -1;
         }
         // copy the (uniform) descriptor word by word into scalar registers
         BatchProblem bp;
         {
-            const uint32_t *src = reinterpret_cast<const uint32_t *>(probs + lo);
+            const uint32_t *src = reinterpret_cast<const uint32_t *>(probs + pi);
             uint32_t *dst = reinterpret_cast<uint32_t *>(&bp);
 #pragma unroll
             for (int w = 0; w < (int)(sizeof(BatchProblem) / 4); ++w)
                 dst[w] = __builtin_amdgcn_readfirstlane(src[w]);
         }
-        const int64_t local = t - bp.tile0;
-        const int64_t tm = local / bp.tiles_n, tn = local - tm * bp.tiles_n;
-        tile_gemm<T, BM, BN, BK, WGM, WGN, EPT, DBUF, ALIGN>(bp.g, tm * BM, tn * BN, sA, sB);
+        if (tm < 0) {
+            const int64_t local = t - bp.tile0;
+            tm = local / bp.tiles_n;
+            tn = local - tm * bp.tiles_n;
+        }
+        // the tile runs gemm_ex's code for its problem's row alignment
+        if (bp.aligned)
+            tile_gemm<T, BM, BN, BK, WGM, WGN, EPT, DBUF, true>(bp.g, tm * BM, tn * BN, sA, sB);
+        else
+            tile_gemm<T, BM, BN, BK, WGM, WGN, EPT, DBUF, false>(bp.g, tm * BM, tn * BN, sA, sB);
+        __syncthreads();                  // every wave has read the current index
+        if (threadIdx.x == 0) next = settle();
+        __syncthreads();
+        t = uniform_next();
     }
 }
 
@@ -647,23 +707,22 @@ hipError_t launch_tiled(const GemmArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <typename T, int BM, int BN, int BK, int WGM, int WGN, int EPT, int DBUF, int OCC,
-          bool ALIGN>
-hipError_t launch_batched(const BatchProblem *probs, int nprob, int64_t total_tiles,
-                          unsigned long long *counter, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((gemm_batched_kernel<T, BM, BN, BK, WGM, WGN, EPT, DBUF, OCC, ALIGN>),
-                       dim3((unsigned)grid), dim3(64 * WGM * WGN), 0, s, probs, nprob, total_tiles,
-                       counter);
+template <typename T, int BM, int BN, int BK, int WGM, int WGN, int EPT, int DBUF, int OCC>
+hipError_t launch_batched(const BatchProblem *probs, const uint64_t *tile_map,
+                          const int64_t *list_off, int nlist, int nprob,
+                          unsigned long long *counters, int grid, hipStream_t s) {
+    hipLaunchKernelGGL((gemm_batched_kernel<T, BM, BN, BK, WGM, WGN, EPT, DBUF, OCC>),
+                       dim3((unsigned)grid), dim3(64 * WGM * WGN), 0, s, probs, tile_map, list_off,
+                       nlist, nprob, counters);
     return hipGetLastError();
 }
 
 // Resident work-groups per compute unit of the batched kernel (occupancy query).
-template <typename T, int BM, int BN, int BK, int WGM, int WGN, int EPT, int DBUF, int OCC,
-          bool ALIGN>
+template <typename T, int BM, int BN, int BK, int WGM, int WGN, int EPT, int DBUF, int OCC>
 int batched_occupancy() {
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &nb, gemm_batched_kernel<T, BM, BN, BK, WGM, WGN, EPT, DBUF, OCC, ALIGN>,
+            &nb, gemm_batched_kernel<T, BM, BN, BK, WGM, WGN, EPT, DBUF, OCC>,
             64 * WGM * WGN, 0) != hipSuccess)
         return 1;
     return nb > 0 ? nb : 1;
@@ -698,19 +757,15 @@ hipError_t launch_pipe(const GemmArgs &a, hipStream_t s) {
     {{BM, BN, BK, WGM * WGN, 16 / (int)sizeof(T), 2, WGM * WGN / 4},                      \
      &launch_pipe<T, BM, BN, BK, WGM, WGN, FWGM, FWGN, FEPT>,                             \
      &launch_tiled<T, BM, BN, BK, FWGM, FWGN, FEPT, 1, 0, false>,                         \
-     {&launch_batched<T, BM, BN, BK, FWGM, FWGN, FEPT, 1, 0, true>,                       \
-      &launch_batched<T, BM, BN, BK, FWGM, FWGN, FEPT, 1, 0, false>},                     \
-     {&batched_occupancy<T, BM, BN, BK, FWGM, FWGN, FEPT, 1, 0, true>,                    \
-      &batched_occupancy<T, BM, BN, BK, FWGM, FWGN, FEPT, 1, 0, false>}}
+     &launch_batched<T, BM, BN, BK, FWGM, FWGN, FEPT, 1, 0>,                               \
+     &batched_occupancy<T, BM, BN, BK, FWGM, FWGN, FEPT, 1, 0>}
 
 #define MGEMM_CFG(T, BM, BN, BK, WGM, WGN, EPT, DBUF, OCC)                              \
     {{BM, BN, BK, WGM * WGN, EPT, DBUF, OCC},                                             \
      &launch_tiled<T, BM, BN, BK, WGM, WGN, EPT, DBUF, OCC, true>,                        \
      &launch_tiled<T, BM, BN, BK, WGM, WGN, EPT, DBUF, OCC, false>,                       \
-     {&launch_batched<T, BM, BN, BK, WGM, WGN, EPT, DBUF, OCC, true>,                     \
-      &launch_batched<T, BM, BN, BK, WGM, WGN, EPT, DBUF, OCC, false>},                   \
-     {&batched_occupancy<T, BM, BN, BK, WGM, WGN, EPT, DBUF, OCC, true>,                  \
-      &batched_occupancy<T, BM, BN, BK, WGM, WGN, EPT, DBUF, OCC, false>}}
+     &launch_batched<T, BM, BN, BK, WGM, WGN, EPT, DBUF, OCC>,                             \
+     &batched_occupancy<T, BM, BN, BK, WGM, WGN, EPT, DBUF, OCC>}
 
 static const KernelEntry kF64[] = {
     MGEMM_CFG(double, 128, 128, 16, 2, 2, 2, 1, 0),

@@ -26,22 +26,36 @@ struct BatchProblem {
     GemmArgs g;
     int64_t tile0;
     int64_t tiles_n;
+    int64_t aligned;    // 1: rows of A and B start on 2-element boundaries
 };
 
-// A registered kernel: its configuration and its launchers.  Index [0] of the
-// batched pairs is the variant for rows starting on 2-element boundaries (even
-// leading dimensions, aligned base pointers), [1] the variant for any rows.
+// A registered kernel: its configuration and its launchers.  The batched kernel
+// takes problems of any row alignment and picks each tile's load path from
+// BatchProblem::aligned.
 typedef hipError_t (*LaunchFn)(const GemmArgs &, hipStream_t);
-typedef hipError_t (*BatchLaunchFn)(const BatchProblem *, int, int64_t, unsigned long long *, int,
-                                    hipStream_t);
+typedef hipError_t (*BatchLaunchFn)(const BatchProblem *, const uint64_t *, const int64_t *, int,
+                                    int, unsigned long long *, int, hipStream_t);
+
+// Work lists of a batched launch: with a tile map, one list per XCD (work-group
+// b starts on list b % BATCH_LISTS, the XCD it runs on, and then takes from the
+// others); without one, a single list of tile numbers.  List l holds entries
+// [off[l], off[l+1]) and has its own counter.
+constexpr int BATCH_LISTS = 8;
+
+// Tile map of a batched launch: entry t packs the problem index of tile t (bits
+// 40-63) and the tile's row and column within that problem (bits 20-39, 0-19).
+constexpr int TILE_MAP_PROB_BITS = 24, TILE_MAP_RC_BITS = 20;
+inline uint64_t tile_map_entry(uint64_t prob, uint64_t tm, uint64_t tn) {
+    return (prob << (2 * TILE_MAP_RC_BITS)) | (tm << TILE_MAP_RC_BITS) | tn;
+}
 typedef int (*OccupancyFn)();
 
 struct KernelEntry {
     mgemm_cfg cfg;
     LaunchFn launch;             // aligned rows
     LaunchFn launch_unaligned;   // any rows
-    BatchLaunchFn batched[2];
-    OccupancyFn batched_occupancy[2];
+    BatchLaunchFn batched;               // any rows (per-problem load path)
+    OccupancyFn batched_occupancy;
 };
 
 // Per-dtype registries, defined in the kernel files.

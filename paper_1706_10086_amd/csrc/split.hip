@@ -556,9 +556,9 @@ split_pairs_i8_pipe_kernel(PairArgs a) {
 // exact FP64 hi / lo sums.  Four LDS stages (one k-chunk of all 6 slices of the
 // tile's 64 A rows and 128 B columns each) are filled by direct global->LDS loads
 // three chunks ahead, spread over the products; fragments are refilled from the
-// next stage right after their last use.  Chunks run in blocks of 16, so each
-// level's flush into hi / lo (after 16, 8, 4, 4, 2, 2 chunks) is placed at compile
-// time; the pass's chunk range is a multiple of 16 (k padded with zero slices).
+// next stage right after their last use.  Each level is flushed into hi / lo at
+// most every 16, 8, 4, 4, 2, 2 chunks; the pass's chunk range is a multiple of
+// 16 (k padded with zero slices).
 constexpr int R_BM = 64, R_BN = 128;
 constexpr int R_THREADS = 512;
 constexpr int R_UNITS = 12;                              // units of one row run (6 x 32 B)
@@ -668,6 +668,11 @@ split_pairs_bf16_pipe_kernel(PairArgs a) {
         fa[s] = __builtin_bit_cast(v8bf, lds[a_off + 2 * s]);
         fb[s] = __builtin_bit_cast(v8bf, lds[b_off + 2 * s]);
     }
+    // Level lv is flushed before chunk c when (c + wm) is a multiple of PERIOD[lv]
+    // and once more after the last chunk, so it never sums more than PERIOD[lv]
+    // chunks.  The one-chunk offset between the two waves of a SIMD (wm = 0, 1)
+    // and the flush at the start of a chunk let one wave's flush run on the
+    // vector unit while the other wave's products keep the matrix core busy.
     constexpr int PERIOD[6] = {16, 8, 4, 4, 2, 2};
     for (int b = 0; b < nch; b += R_BLOCK) {
 #pragma unroll 1
@@ -676,15 +681,18 @@ split_pairs_bf16_pipe_kernel(PairArgs a) {
             if (full_loads) __builtin_amdgcn_s_waitcnt(vmcnt_imm(R_LOADS));
             else __builtin_amdgcn_s_waitcnt(vmcnt_imm(R_LOADS - 1));
             __syncthreads();
+            const int ph = u + wm;                // b is a multiple of every period
+#pragma unroll
+            for (int lv = 0; lv < 6; ++lv)
+                if ((ph & (PERIOD[lv] - 1)) == 0) flush(lv);
             const uint32_t next = c0 + (uint32_t)(b + u + 3);
             // chunk c+3 into the stage of chunk c-1 (past the end: the last
             // chunk again, in bounds and never used)
             products(lds + ((u + 1) & 3) * R_STAGE, next <= clast ? next : clast, (u + 3) & 3);
-#pragma unroll
-            for (int lv = 0; lv < 6; ++lv)
-                if ((u + 1) % PERIOD[lv] == 0) flush(lv);
         }
     }
+#pragma unroll
+    for (int lv = 0; lv < 6; ++lv) flush(lv);
     __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));     // no load lands after this point
 
     // exact value = hi 2^-34 + lo 2^-61, rounded once
