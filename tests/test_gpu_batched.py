@@ -162,3 +162,45 @@ def test_uneven_batch_2048(dev, orc):
         err = np.linalg.norm(Cs[i].cpu().numpy() - ref) / np.linalg.norm(ref)
         assert err <= 1e-13, (i, err)
     plan.destroy()
+
+
+def test_plan_without_tile_map(dev, orc):
+    """A problem with 2^20 + 1 tile rows (m = 2^25 + 5 with 32-row tiles) does not fit
+    the tile map's fields, so the plan's kernels find each tile's problem by binary
+    search over one list of tile numbers: still bitwise equal to per-problem gemm_ex
+    with the same configurations, and sampled rows of the tall problem match the
+    oracle."""
+    cfgs = mg.configs(mg.F64)
+    c32 = [c for c in cfgs if c.bm == 32][0]
+    c64 = [c for c in cfgs if (c.bm, c.bn, c.bk) == (64, 64, 16)][0]
+    m_tall = (1 << 25) + 5
+    say(f"batched plan without tile map: tall problem m={m_tall}, 32x32 tiles")
+    g = torch.Generator(device=dev)
+    g.manual_seed(91)
+    shapes = [(m_tall, 3, 2, c32), (100, 70, 50, c32), (65, 130, 33, c64), (7, 5, 300, c64),
+              (1, 1, 1, c32)]
+    As = [torch.rand((m, k), device=dev, dtype=torch.float64, generator=g) * 2 - 1
+          for m, n, k, _ in shapes]
+    Bs = [torch.rand((k, n), device=dev, dtype=torch.float64, generator=g) * 2 - 1
+          for m, n, k, _ in shapes]
+    Cs = [torch.rand((m, n), device=dev, dtype=torch.float64, generator=g) for m, n, k, _ in shapes]
+    Cr = [c.clone() for c in Cs]
+    rows = torch.tensor([0, 31, 32, 1 << 20, (1 << 25) - 1, 1 << 25, m_tall - 1], device=dev)
+    C0 = Cs[0][rows].cpu().numpy()
+    pick = [s[3] for s in shapes]
+    plan = mg.BatchedPlan(As, Bs, Cs, 1.25, -0.5, cfgs=pick)
+    info = plan.info()
+    say(f"  plan {info}")
+    assert info["buckets"] == 2 and info["tiles"] > (1 << 20)
+    plan.execute()
+    for a, b, c, cfg in zip(As, Bs, Cr, pick):
+        mg.gemm(a, b, c, 1.25, -0.5, cfg=cfg)
+    torch.cuda.synchronize()
+    for i, (c, r) in enumerate(zip(Cs, Cr)):
+        assert torch.equal(c, r), i
+    want = orc.gemm_f64(1.25, As[0][rows].cpu().numpy(), Bs[0].cpu().numpy(), -0.5, C0)
+    got = Cs[0][rows].cpu().numpy()
+    assert np.linalg.norm(got - want) <= 1e-13 * np.linalg.norm(want)
+    plan.destroy()
+    del As, Bs, Cs, Cr
+    torch.cuda.empty_cache()
