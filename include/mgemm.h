@@ -82,9 +82,10 @@ enum {
  *   double_buffer     1: two LDS stages, the next k-step's tiles are loaded while
  *                     the current one is multiplied; 0: one stage; 2: three
  *                     stages filled by direct global->LDS loads two k-steps
- *                     ahead (FP64 only; needs n, lda and ldb even and 16-byte
- *                     aligned A and B, else the two-stage kernel of the same
- *                     tile runs, with the same results).
+ *                     ahead (needs n, lda and ldb multiples of the 16-byte load,
+ *                     2 FP64 or 4 FP32 elements, and 16-byte aligned A and B,
+ *                     else the two-stage kernel of the same tile runs, with the
+ *                     same results).
  *   occupancy         wavefronts per SIMD the kernel is compiled to allow (0: the
  *                     compiler's choice, else 1 or 2) -- the GPU counterpart of
  *                     the paper's hardware threads per core (Sec. 3, Tab. 4).
@@ -102,6 +103,15 @@ MGEMM_API int32_t gemm(int64_t m, int64_t n, int64_t k, double alpha,
 /* gemm with an explicit configuration (cfg == NULL: the library's choice; a cfg
  * that is not in the registry for dtype gives -13) and stream (argument 14,
  * a hipStream_t; NULL: the current library stream).
+ *
+ * Split-k (MGEMM_F64, cfg == NULL only): when the chosen tile leaves fewer than
+ * about four work-groups per compute unit and k >= 512, k is cut into S <= 16
+ * ranges (multiples of 256); their partial products go to the library-owned
+ * device workspace (S*m*n*8 bytes, grown on demand, MGEMM_ERR_NOMEM if it
+ * cannot be, kept until mgemm_release_workspace(); calls on one device that use
+ * it are ordered through it) and one kernel adds them in range order and applies
+ * alpha and beta.  Results are deterministic; they can differ in the last bits
+ * from the same tile run with an explicit cfg (another summation order).
  *
  * Split dtypes: A and B are scaled per row / column by powers of two, sliced
  * into small integers and multiplied on matrix cores with exact accumulation;
@@ -233,7 +243,8 @@ MGEMM_API int32_t mgemm_config_count(int32_t dtype);
 /* Copies registered configuration i of dtype into *out; 0 or -2 / -3. */
 MGEMM_API int32_t mgemm_config_get(int32_t dtype, int32_t i, mgemm_cfg *out);
 
-/* Frees the split-path workspace of the current device; 0 on success. */
+/* Frees the library-owned workspace of the current device (split dtypes and
+ * FP64 split-k), after the work that uses it; 0 on success. */
 MGEMM_API int32_t mgemm_release_workspace(void);
 
 /* Diagnostic: one matrix-core step on one wave with the fragment layout the

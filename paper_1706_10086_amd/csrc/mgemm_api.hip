@@ -10,6 +10,8 @@
 #include <mutex>
 #include <string>
 
+#include <algorithm>
+
 #include "mgemm_internal.h"
 
 namespace mgemm {
@@ -192,6 +194,51 @@ const KernelEntry *choose_entry(int32_t dtype, int64_t m, int64_t n, const mgemm
 
 int32_t split_gemm(const GemmArgs &a, int32_t dtype, hipStream_t s);
 
+// Split-k for the built-in choice: when the chosen tile (one with a split-k
+// kernel) leaves fewer than about four work-groups per compute unit, k is cut
+// into S ranges of at least SPLITK_MIN_K (a multiple of every tile's BK) so that
+// about four run per compute unit; the S partial products go to the library
+// workspace and one reduction kernel adds them in order and applies alpha and
+// beta.
+constexpr int64_t SPLITK_MIN_K = 256;
+constexpr int SPLITK_MAX = 16;
+
+static int compute_units() {
+    static int cached[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+    if (!cached[dev]) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            return 0;
+        cached[dev] = cus;
+    }
+    return cached[dev];
+}
+
+static int splitk_factor(int64_t m, int64_t n, int64_t k, const mgemm_cfg &c) {
+    const int cus = compute_units();
+    const int64_t tiles = tiles_of(m, n, c);
+    if (cus <= 0 || tiles <= 0) return 1;
+    int64_t S = (4 * (int64_t)cus + tiles - 1) / tiles;
+    S = std::min<int64_t>(S, k / SPLITK_MIN_K);
+    S = std::min<int64_t>(S, SPLITK_MAX);
+    return S > 1 ? (int)S : 1;
+}
+
+static int32_t run_splitk(const KernelEntry *e, const GemmArgs &a, int32_t dtype, bool al, int S,
+                          hipStream_t s) {
+    // k per range: a multiple of SPLITK_MIN_K, so that the last range is the short one
+    const int64_t kc = ((a.k + S - 1) / S + SPLITK_MIN_K - 1) / SPLITK_MIN_K * SPLITK_MIN_K;
+    S = (int)((a.k + kc - 1) / kc);
+    const size_t es = dtype == MGEMM_F32 ? 4 : 8;
+    return with_workspace((size_t)S * a.m * a.n * es, s, [&](uint8_t *W) -> int32_t {
+        hipError_t he = e->splitk[al ? 0 : 1](a, S, kc, W, s);
+        if (he == hipSuccess) he = splitk_reduce(dtype, W, S, a, s);
+        return he == hipSuccess ? 0 : hip_error(he, "split-k launch");
+    });
+}
+
 }  // namespace mgemm
 
 using namespace mgemm;
@@ -218,6 +265,10 @@ int32_t gemm_ex(int64_t m, int64_t n, int64_t k, double alpha, const void *A, in
     const KernelEntry *e = choose_entry(dtype, m, n, cfg, &err);
     if (!e) return err;
     const bool al = rows_aligned(A, lda, B, ldb, dtype);
+    if (!cfg && e->splitk[0]) {
+        const int S = splitk_factor(m, n, k, e->cfg);
+        if (S > 1) return run_splitk(e, a, dtype, al, S, s);
+    }
     hipError_t he = (al ? e->launch : e->launch_unaligned)(a, s);
     if (he != hipSuccess) return hip_error(he, "gemm launch");
     return 0;

@@ -1,6 +1,8 @@
 // Internal declarations shared by the HIP kernel files and the C-ABI layer.
 #pragma once
 
+#include <functional>
+
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -49,6 +51,9 @@ inline uint64_t tile_map_entry(uint64_t prob, uint64_t tm, uint64_t tn) {
     return (prob << (2 * TILE_MAP_RC_BITS)) | (tm << TILE_MAP_RC_BITS) | tn;
 }
 typedef int (*OccupancyFn)();
+// Split-k partial products: (GEMM, number of splits S, k per split, W): plane y of
+// W (m x n, row stride n) receives the product over k range [y*kc, (y+1)*kc).
+typedef hipError_t (*SplitkLaunchFn)(const GemmArgs &, int, int64_t, void *, hipStream_t);
 
 struct KernelEntry {
     mgemm_cfg cfg;
@@ -56,6 +61,8 @@ struct KernelEntry {
     LaunchFn launch_unaligned;   // any rows
     BatchLaunchFn batched;               // any rows (per-problem load path)
     OccupancyFn batched_occupancy;
+    SplitkLaunchFn splitk[2];            // split-k partials, [0] aligned rows, [1] any
+                                         // rows; null where the tile has none
 };
 
 // Per-dtype registries, defined in the kernel files.
@@ -100,6 +107,14 @@ constexpr int CRT_KSTEP = 64;
 int crt_operand_bits(int64_t k);
 hipError_t crt_launch(const GemmArgs &g, hipStream_t s, const int *e, const int *fexp, int bits,
                       int8_t *QA, int8_t *QB, uint8_t *R, int64_t mp, int64_t np, int64_t kp);
+
+// C = alpha * (sum of the S partial planes of W, in plane order) + beta * C.
+hipError_t splitk_reduce(int32_t dtype, const void *W, int S, const GemmArgs &a, hipStream_t s);
+
+// Runs fn on the current device's library-owned workspace grown to at least
+// `bytes`, ordered on stream s after the workspace's previous user; returns fn's
+// result (or an allocation error).
+int32_t with_workspace(size_t bytes, hipStream_t s, const std::function<int32_t(uint8_t *)> &fn);
 
 // s_waitcnt immediate for vmcnt(n) (n < 64), no wait on the other counters.
 constexpr int vmcnt_imm(int n) { return (n & 15) | ((n >> 4) << 14) | 0x70 | 0xF00; }

@@ -903,6 +903,21 @@ int32_t split_gemm(const GemmArgs &g, int32_t dtype, hipStream_t s) {
     return set_error(MGEMM_ERR_NOCONFIG, "split dtype %d is not built", dtype);
 }
 
+int32_t with_workspace(size_t bytes, hipStream_t s, const std::function<int32_t(uint8_t *)> &fn) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES)
+        return set_error(MGEMM_ERR_HIP, "workspace: no current device");
+    Workspace &w = g_ws[dev];
+    std::lock_guard<std::mutex> lock(w.mtx);
+    int32_t rc = ws_reserve(w, bytes);
+    if (rc) return rc;
+    hipError_t he = hipStreamWaitEvent(s, w.done, 0);
+    if (he != hipSuccess) return set_error(MGEMM_ERR_HIP, "workspace: %s", hipGetErrorString(he));
+    rc = fn(w.base);
+    hipEventRecord(w.done, s);
+    return rc;
+}
+
 int32_t split_release() {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return 0;

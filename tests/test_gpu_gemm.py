@@ -175,6 +175,48 @@ def test_fp32_within_gamma_bound(dev, orc):
         assert err < 1e-6
 
 
+SPLITK_SHAPES = [(1024, 1024, 1024), (1000, 999, 3001), (37, 45, 5000), (64, 1024, 777),
+                 (1, 1, 70000), (300, 200, 600), (511, 130, 513)]
+
+
+@pytest.mark.parametrize("dtype", [mg.F64])
+def test_split_k_default_choice(dev, orc, dtype):
+    """FP64 outputs whose chosen tile leaves fewer than about four work-groups per
+    compute unit, with k >= 512, run split-k under the built-in choice (k cut into
+    ranges of 256j, partial products reduced in order): every element within
+    gamma_{k+2} of the double-double oracle, normwise <= 1e-13, run-to-run
+    identical, C not read when beta = 0."""
+    u = 2.0 ** -24 if dtype == mg.F32 else 2.0 ** -53
+    for (m, n, k) in SPLITK_SHAPES:
+        say(f"split-k default choice {'f32' if dtype == mg.F32 else 'f64'} shape={(m, n, k)}")
+        A = synth.uniform_pm1((m, k), 21 + m)
+        B = synth.uniform_pm1((k, n), 22 + n)
+        C = synth.uniform_pm1((m, n), 23 + k)
+        if dtype == mg.F32:
+            A, B, C = (x.astype(np.float32).astype(np.float64) for x in (A, B, C))
+        al, be = (np.float32(1.5), np.float32(-0.5)) if dtype == mg.F32 else (1.5, -0.5)
+        got = run_gemm(dev, A, B, C, 1.5, -0.5, dtype=dtype)
+        ref = orc.gemm_dot2(al, A, B, be, C, nthreads=orc.num_procs())
+        bound = gamma(k + 2, u) * (1.5 * np.abs(A) @ np.abs(B) + 0.5 * np.abs(C))
+        assert np.all(np.abs(got - ref) <= bound), (m, n, k)
+        if dtype == mg.F64:
+            assert np.linalg.norm(got - ref) <= 1e-13 * np.linalg.norm(ref)
+        again = run_gemm(dev, A, B, C, 1.5, -0.5, dtype=dtype)
+        assert np.array_equal(got, again)
+        nan_c = run_gemm(dev, A, B, np.full((m, n), np.nan), 1.5, 0.0, dtype=dtype)
+        assert np.all(np.isfinite(nan_c))
+    # the 1024^3 product really took the split path: its summation order differs from
+    # the same tile run whole (an explicit configuration never splits k)
+    n = 1024
+    A = synth.uniform_pm1((n, n), 31)
+    B = synth.uniform_pm1((n, n), 32)
+    whole_cfg = [c for c in mg.configs(dtype) if (c.bm, c.bn, c.bk, c.waves) == (64, 64, 16, 4)][0]
+    split = run_gemm(dev, A, B, np.zeros((n, n)), 1.0, 0.0, dtype=dtype)
+    whole = run_gemm(dev, A, B, np.zeros((n, n)), 1.0, 0.0, dtype=dtype, cfg=whole_cfg)
+    assert not np.array_equal(split, whole)
+    assert np.linalg.norm(split - whole) <= 4 * n * u * np.linalg.norm(whole)
+
+
 def test_run_to_run_determinism(dev):
     say("determinism 1024^3")
     n = 1024
