@@ -134,8 +134,10 @@ def test_plan_rejects_bad_problems(dev):
 
 def test_uneven_batch_2048(dev, orc):
     """The batched workload: 2048 problems with m, n, k log-uniform in [16, 1024],
-    alpha = 1, beta = 0; plan vs per-problem launches bitwise, sampled problems
-    against the oracle."""
+    alpha = 1, beta = 0; the plan (every problem on the 64 x 64 x 16 tile) bitwise
+    against per-problem gemm_ex with that configuration; per-problem launches with
+    the library's choice (which splits k for some small outputs) within 1e-13;
+    sampled problems against the oracle."""
     say("batched 2048 uneven: building inputs on the device")
     cnt = 2048
     ms = synth.log_uniform_int(cnt, 4001, 16, 1024)
@@ -149,13 +151,18 @@ def test_uneven_batch_2048(dev, orc):
           for k, n in zip(ks, ns)]
     Cs = [torch.zeros((int(m), int(n)), device=dev, dtype=torch.float64) for m, n in zip(ms, ns)]
     Cr = [torch.zeros_like(c) for c in Cs]
+    Cd = [torch.zeros_like(c) for c in Cs]
     plan = mg.BatchedPlan(As, Bs, Cs, 1.0, 0.0)
     say(f"  plan {plan.info()}")
     plan.execute()
-    mg.gemm_batched(As, Bs, Cr, 1.0, 0.0)
+    c64 = [c for c in mg.configs(mg.F64) if (c.bm, c.bn, c.bk, c.waves) == (64, 64, 16, 4)][0]
+    for a, b, c in zip(As, Bs, Cr):
+        mg.gemm(a, b, c, 1.0, 0.0, cfg=c64)
+    mg.gemm_batched(As, Bs, Cd, 1.0, 0.0)
     torch.cuda.synchronize()
     for i in range(cnt):
         assert torch.equal(Cs[i], Cr[i]), i
+        assert torch.linalg.norm(Cs[i] - Cd[i]) <= 1e-13 * torch.linalg.norm(Cs[i]), i
     for i in (0, 1, 777, 2047):
         A, B = As[i].cpu().numpy(), Bs[i].cpu().numpy()
         ref = orc.gemm_f64(1.0, A, B)
