@@ -192,3 +192,41 @@ def test_extreme_exponents(dev, orc, dtype):
             want = orc.split_gemm(1.0, A, B, fmt=fmt, S=S)
         bad = np.argwhere(got != want)
         assert bad.size == 0, (ea, eb, bad[:5], got[tuple(bad[0])], want[tuple(bad[0])])
+
+
+def test_bf16_operands_beyond_4gib(dev, orc):
+    """bf16 slices of A beyond 4 GiB (m = 16384, k = 24576: 12 bytes per element)
+    take the register-staged pair kernel with 64-bit addresses: sampled rows
+    bitwise equal to the oracle's split model.  int8 slices beyond 4 GiB are
+    refused with MGEMM_ERR_NOCONFIG before any operand is read."""
+    m, n, k = 16384, 256, 24576
+    say(f"split bf16 beyond 4 GiB: {(m, n, k)}, inputs on the device")
+    g = torch.Generator(device=dev)
+    g.manual_seed(61)
+    u = torch.rand((m, k), device=dev, dtype=torch.float64, generator=g) * 2 - 1
+    e = torch.randint(-20, 21, (m, k), device=dev, generator=g)
+    tA = torch.ldexp(u, e)
+    del u, e
+    B = synth.wide_range((k, n), 62)
+    tB = torch.from_numpy(B).to(dev)
+    tC = torch.zeros((m, n), device=dev, dtype=torch.float64)
+    mg.gemm(tA, tB, tC, 1.0, 0.0, dtype=mg.SPLIT_BF16)
+    torch.cuda.synchronize()
+    rows = torch.tensor([0, 1, 4095, 8191, 12000, m - 1], device=dev)
+    got = tC[rows].cpu().numpy()
+    say("  oracle split model on sampled rows")
+    fmt, S = FMT[mg.SPLIT_BF16]
+    want = orc.split_gemm(1.0, tA[rows].cpu().numpy(), B, fmt=fmt, S=S, nthreads=orc.num_procs())
+    assert np.array_equal(got, want)
+    del tA, tB, tC
+    mg.release_workspace()
+    torch.cuda.empty_cache()
+    # int8: 16384 x 32768 x 8 slices = 2^32 bytes
+    t = torch.empty((16384, 32768), device=dev, dtype=torch.float64)
+    b = torch.zeros((32768, 8), device=dev, dtype=torch.float64)
+    c = torch.zeros((16384, 8), device=dev, dtype=torch.float64)
+    with pytest.raises(mg.MgemmError) as ei:
+        mg.gemm(t, b, c, 1.0, 0.0, dtype=mg.SPLIT_INT8)
+    assert ei.value.code == mg.ERR_NOCONFIG
+    del t, b, c
+    torch.cuda.empty_cache()
