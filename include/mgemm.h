@@ -179,7 +179,8 @@ MGEMM_API int32_t gemm_batched_plan_create(int64_t count, const int64_t *m, cons
  * Executions of one plan must not overlap (they share the work counters). */
 MGEMM_API int32_t gemm_batched_plan_execute(void *plan);
 
-/* Waits for the plan's stream and frees the plan (NULL is a no-op). */
+/* Waits for the plan's stream and frees the plan (NULL is a no-op); returns
+ * MGEMM_ERR_HIP if that wait reported an error (the plan is freed anyway). */
 MGEMM_API int32_t gemm_batched_plan_destroy(void *plan);
 
 /* Number of configuration groups, total C tiles and total 2*m*n*k of a plan. */
@@ -227,7 +228,8 @@ MGEMM_API int32_t mlp_forward(void *mlp, int64_t rows, const float *X, float *Y)
  * ties, -1 when no entry is allowed); X, M, idx device. */
 MGEMM_API int32_t mlp_predict(void *mlp, int64_t rows, const float *X, const float *M,
                               int32_t *idx);
-/* Frees the model (NULL is a no-op). */
+/* Waits for the library stream and frees the model (NULL is a no-op); returns
+ * MGEMM_ERR_HIP if that wait reported an error (the model is freed anyway). */
 MGEMM_API int32_t mlp_destroy(void *mlp);
 
 /* Sets the stream used when a call passes NULL; returns 0. */
@@ -244,7 +246,8 @@ MGEMM_API int32_t mgemm_config_count(int32_t dtype);
 MGEMM_API int32_t mgemm_config_get(int32_t dtype, int32_t i, mgemm_cfg *out);
 
 /* Frees the library-owned workspace of the current device (split dtypes and
- * FP64 split-k), after the work that uses it; 0 on success. */
+ * FP64 split-k) once the work that last used it has finished; 0 on success,
+ * MGEMM_ERR_HIP (workspace kept) if waiting for that work fails. */
 MGEMM_API int32_t mgemm_release_workspace(void);
 
 /* Diagnostic: one matrix-core step on one wave with the fragment layout the

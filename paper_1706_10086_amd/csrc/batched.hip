@@ -103,9 +103,10 @@ struct Plan {
 
 static void plan_free(Plan *p) {
     if (!p) return;
-    if (p->exec) hipGraphExecDestroy(p->exec);
-    if (p->graph) hipGraphDestroy(p->graph);
-    if (p->dev) hipFree(p->dev);
+    // teardown: nothing more can be done about a failure here
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->dev) (void)hipFree(p->dev);
     delete p;
 }
 
@@ -172,7 +173,13 @@ int32_t gemm_batched_plan_create(int64_t count, const int64_t *m, const int64_t 
     p->dtype = dtype;
     p->stream = (hipStream_t)stream;
     p->count = count;
-    hipGetDevice(&p->device);
+    {
+        hipError_t de = hipGetDevice(&p->device);
+        if (de != hipSuccess) {
+            plan_free(p);
+            return hip_fail(de, "plan: no current device");
+        }
+    }
 
     // bucket by configuration
     std::map<const KernelEntry *, size_t> index;
@@ -214,8 +221,9 @@ int32_t gemm_batched_plan_create(int64_t count, const int64_t *m, const int64_t 
     }
 
     int cus = 0;
-    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);
-    if (cus <= 0) cus = 1;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess ||
+        cus <= 0)
+        cus = 1;   // a smaller persistent grid is still correct
     size_t bytes = 0;
     for (Bucket &b : p->buckets) {
         const mgemm_cfg &c = b.entry->cfg;
@@ -309,18 +317,21 @@ int32_t gemm_batched_plan_create(int64_t count, const int64_t *m, const int64_t 
     if (he == hipSuccess) {
         hipLaunchKernelGGL(reset_counters_kernel, dim3((unsigned)((ncounters + 63) / 64)),
                            dim3(64), 0, cs, counters, ncounters);
-        hipEventRecord(start, cs);
+        hipError_t ge = hipEventRecord(start, cs);
+        if (ge != hipSuccess && rc == 0) rc = hip_fail(ge, "plan: capture record");
         for (int b = 0; b < nb; ++b) {
             Bucket &bk = p->buckets[b];
-            hipStreamWaitEvent(branch[b], start, 0);
+            ge = hipStreamWaitEvent(branch[b], start, 0);
+            if (ge != hipSuccess && rc == 0) rc = hip_fail(ge, "plan: capture fork");
             hipError_t le = bk.entry->batched(
                 (const BatchProblem *)(p->dev + bk.offset),
                 bk.use_map ? (const uint64_t *)(p->dev + bk.map_offset) : nullptr,
                 (const int64_t *)(p->dev + bk.list_offset), (int)bk.list_off.size() - 1,
                 (int)bk.probs.size(), counters + (size_t)b * BATCH_LISTS, bk.grid, branch[b]);
             if (le != hipSuccess && rc == 0) rc = hip_fail(le, "plan: bucket launch");
-            hipEventRecord(done[b], branch[b]);
-            hipStreamWaitEvent(cs, done[b], 0);
+            ge = hipEventRecord(done[b], branch[b]);
+            if (ge == hipSuccess) ge = hipStreamWaitEvent(cs, done[b], 0);
+            if (ge != hipSuccess && rc == 0) rc = hip_fail(ge, "plan: capture join");
         }
         hipError_t ce = hipStreamEndCapture(cs, &p->graph);
         if (ce != hipSuccess && rc == 0) rc = hip_fail(ce, "plan: capture");
@@ -332,11 +343,11 @@ int32_t gemm_batched_plan_create(int64_t count, const int64_t *m, const int64_t 
         rc = hip_fail(he, "plan: stream setup");
     }
     for (int b = 0; b < nb; ++b) {
-        if (done[b]) hipEventDestroy(done[b]);
-        if (branch[b]) hipStreamDestroy(branch[b]);
+        if (done[b]) (void)hipEventDestroy(done[b]);
+        if (branch[b]) (void)hipStreamDestroy(branch[b]);
     }
-    if (start) hipEventDestroy(start);
-    if (cs) hipStreamDestroy(cs);
+    if (start) (void)hipEventDestroy(start);
+    if (cs) (void)hipStreamDestroy(cs);
     if (rc) {
         plan_free(p);
         return rc;
@@ -355,9 +366,9 @@ int32_t gemm_batched_plan_execute(void *plan) {
 int32_t gemm_batched_plan_destroy(void *plan) {
     Plan *p = (Plan *)plan;
     if (!p) return 0;
-    hipStreamSynchronize(p->stream);
+    const hipError_t he = hipStreamSynchronize(p->stream);   // the plan's last launch
     plan_free(p);
-    return 0;
+    return he == hipSuccess ? 0 : hip_fail(he, "plan destroy: stream synchronize");
 }
 
 int32_t gemm_batched_plan_info(void *plan, int32_t *buckets, int64_t *total_tiles, double *flops) {

@@ -186,12 +186,13 @@ static unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 static void free_data(Mlp *p) {
     float **bufs[] = {&p->X, &p->T, &p->M, &p->z1, &p->h1, &p->z2, &p->h2, &p->y, &p->dy, &p->dz2,
                       &p->dz1};
+    // teardown: nothing more can be done about a failure here
     for (float **b : bufs) {
-        if (*b) hipFree(*b);
+        if (*b) (void)hipFree(*b);
         *b = nullptr;
     }
-    if (p->exec) hipGraphExecDestroy(p->exec);
-    if (p->graph) hipGraphDestroy(p->graph);
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
     p->exec = nullptr;
     p->graph = nullptr;
     p->B = 0;
@@ -360,8 +361,8 @@ int32_t mlp_train(void *handle, int32_t steps, float lr, float beta1, float beta
     hipError_t e = hipSuccess;
     // one training step, captured once per hyper-parameter set
     if (!p->exec || p->g_lr != lr || p->g_b1 != beta1 || p->g_b2 != beta2 || p->g_eps != eps) {
-        if (p->exec) hipGraphExecDestroy(p->exec);
-        if (p->graph) hipGraphDestroy(p->graph);
+        if (p->exec) (void)hipGraphExecDestroy(p->exec);
+        if (p->graph) (void)hipGraphDestroy(p->graph);
         p->exec = nullptr;
         p->graph = nullptr;
         hipStream_t cs;
@@ -375,7 +376,7 @@ int32_t mlp_train(void *handle, int32_t steps, float lr, float beta1, float beta
             e = hipStreamEndCapture(cs, &p->graph);
         }
         if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
-        hipStreamDestroy(cs);
+        (void)hipStreamDestroy(cs);
         if (e != hipSuccess) return hip_err(e, "mlp: training graph");
         p->g_lr = lr;
         p->g_b1 = beta1;
@@ -403,7 +404,7 @@ int32_t mlp_forward(void *handle, int64_t rows, const float *X, float *Y) {
     mlp_forward_launch(p, B, X, (float *)nullptr, tmp, (float *)nullptr, tmp + B * p->H, Y, s);
     e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    hipFree(tmp);
+    (void)hipFree(tmp);
     return e == hipSuccess ? 0 : hip_err(e, "mlp_forward");
 }
 
@@ -427,21 +428,21 @@ int32_t mlp_predict(void *handle, int64_t rows, const float *X, const float *M, 
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) rc = hip_err(e, "mlp_predict");
     }
-    hipFree(y);
+    (void)hipFree(y);
     return rc;
 }
 
 int32_t mlp_destroy(void *handle) {
     Mlp *p = (Mlp *)handle;
     if (!p) return 0;
-    hipStreamSynchronize(current_stream());
+    const hipError_t e = hipStreamSynchronize(current_stream());   // work that uses p
     free_data(p);
     float **bufs[] = {&p->par, &p->grad, &p->m, &p->v, &p->loss};
     for (float **b : bufs)
-        if (*b) hipFree(*b);
-    if (p->step) hipFree(p->step);
+        if (*b) (void)hipFree(*b);
+    if (p->step) (void)hipFree(p->step);
     delete p;
-    return 0;
+    return e == hipSuccess ? 0 : hip_err(e, "mlp_destroy: stream synchronize");
 }
 
 }  // extern "C"

@@ -718,6 +718,15 @@ struct Workspace {
 
 static Workspace g_ws[MAX_DEVICES];
 
+// Marks the workspace in use until the work just queued on s has finished; if
+// the event cannot be recorded, waits for that work instead.
+static int32_t ws_mark(Workspace &w, hipStream_t s) {
+    if (hipEventRecord(w.done, s) == hipSuccess) return 0;
+    (void)hipGetLastError();
+    const hipError_t he = hipStreamSynchronize(s);
+    return he == hipSuccess ? 0 : set_error(MGEMM_ERR_HIP, "workspace: %s", hipGetErrorString(he));
+}
+
 static int32_t ws_reserve(Workspace &w, size_t bytes) {
     if (!w.done) {
         if (hipEventCreateWithFlags(&w.done, hipEventDisableTiming) != hipSuccess)
@@ -729,8 +738,11 @@ static int32_t ws_reserve(Workspace &w, size_t bytes) {
     }
     if (w.bytes >= bytes) return 0;
     if (w.base) {
-        hipEventSynchronize(w.done);
-        hipFree(w.base);
+        // the old buffer is freed only once its last user has finished
+        const hipError_t he = hipEventSynchronize(w.done);
+        if (he != hipSuccess)
+            return set_error(MGEMM_ERR_HIP, "workspace: %s", hipGetErrorString(he));
+        (void)hipFree(w.base);
         w.base = nullptr;
         w.bytes = 0;
     }
@@ -825,8 +837,7 @@ static int32_t run_split(const GemmArgs &g, hipStream_t s, Workspace &w, int max
     }
     he = hipGetLastError();
     if (he != hipSuccess) return set_error(MGEMM_ERR_HIP, "split launch: %s", hipGetErrorString(he));
-    hipEventRecord(w.done, s);
-    return 0;
+    return ws_mark(w, s);
 }
 
 // Modular-integer emulation: the scale step above, then the residue, product and
@@ -868,8 +879,7 @@ static int32_t run_crt(const GemmArgs &g, hipStream_t s, Workspace &w) {
 
     he = crt_launch(g, s, e, fexp, crt_operand_bits(g.k), QA, QB, R, mp, np, kp);
     if (he != hipSuccess) return set_error(MGEMM_ERR_HIP, "crt launch: %s", hipGetErrorString(he));
-    hipEventRecord(w.done, s);
-    return 0;
+    return ws_mark(w, s);
 }
 
 int32_t split_gemm(const GemmArgs &g, int32_t dtype, hipStream_t s) {
@@ -914,8 +924,8 @@ int32_t with_workspace(size_t bytes, hipStream_t s, const std::function<int32_t(
     hipError_t he = hipStreamWaitEvent(s, w.done, 0);
     if (he != hipSuccess) return set_error(MGEMM_ERR_HIP, "workspace: %s", hipGetErrorString(he));
     rc = fn(w.base);
-    hipEventRecord(w.done, s);
-    return rc;
+    const int32_t mrc = ws_mark(w, s);
+    return rc ? rc : mrc;
 }
 
 int32_t split_release() {
@@ -924,8 +934,10 @@ int32_t split_release() {
     Workspace &w = g_ws[dev];
     std::lock_guard<std::mutex> lock(w.mtx);
     if (w.base) {
-        hipEventSynchronize(w.done);
-        hipFree(w.base);
+        const hipError_t he = hipEventSynchronize(w.done);
+        if (he != hipSuccess)
+            return set_error(MGEMM_ERR_HIP, "workspace release: %s", hipGetErrorString(he));
+        (void)hipFree(w.base);
         w.base = nullptr;
         w.bytes = 0;
     }
