@@ -174,6 +174,23 @@ def dtype_of(t) -> int:
     raise ValueError(f"unsupported tensor dtype {t.dtype}")
 
 
+def _check_operands(dtype: int, *ts) -> None:
+    """The C ABI takes bare device pointers, so the element type and the device
+    are checked here: FP32 needs float32 tensors, every other dtype float64, all
+    on the current GPU."""
+    import torch
+    want = torch.float32 if dtype == F32 else torch.float64
+    dev = torch.cuda.current_device() if torch.cuda.is_available() else None
+    for t in ts:
+        if not isinstance(t, torch.Tensor):
+            raise TypeError("torch tensors expected")
+        if t.dtype != want:
+            raise ValueError(f"{DTYPE_NAMES.get(dtype, dtype)} takes {want} tensors, got {t.dtype}")
+    for t in ts:
+        if not t.is_cuda or t.device.index != dev:
+            raise ValueError("tensors must live on the current GPU")
+
+
 def gemm(A, B, C, alpha: float = 1.0, beta: float = 0.0, dtype: int | None = None,
          cfg=None, stream=None):
     """C <- alpha*A@B + beta*C on the GPU, in place; returns C.
@@ -187,6 +204,7 @@ def gemm(A, B, C, alpha: float = 1.0, beta: float = 0.0, dtype: int | None = Non
         raise ValueError("shape mismatch")
     if dtype is None:
         dtype = dtype_of(A)
+    _check_operands(dtype, A, B, C)
     s = _stream_handle(stream)
     _check(gemm_ex_raw(m, n, k, float(alpha), A.data_ptr(), _ld(A), B.data_ptr(), _ld(B),
                        float(beta), C.data_ptr(), _ld(C), dtype, cfg, s))
@@ -247,8 +265,9 @@ def gemm_batched(As, Bs, Cs, alphas=1.0, betas=0.0, dtype=None) -> None:
     """C_i <- alpha_i A_i B_i + beta_i C_i, one library launch per problem."""
     if not As:
         return
-    arrs = _BatchArrays(As, Bs, Cs, alphas, betas)
     dtype = dtype_of(As[0]) if dtype is None else dtype
+    _check_operands(dtype, *As, *Bs, *Cs)
+    arrs = _BatchArrays(As, Bs, Cs, alphas, betas)
     _check(lib().gemm_batched(*arrs.args(), dtype))
 
 
@@ -257,8 +276,10 @@ class BatchedPlan:
     ``cfgs``: None (library choice) or one Cfg / tuple per problem."""
 
     def __init__(self, As, Bs, Cs, alphas=1.0, betas=0.0, dtype=None, cfgs=None, stream=None):
-        self._arrs = _BatchArrays(As, Bs, Cs, alphas, betas)
         self.dtype = dtype_of(As[0]) if dtype is None and As else (dtype or F64)
+        if self.dtype in (F64, F32):
+            _check_operands(self.dtype, *As, *Bs, *Cs)
+        self._arrs = _BatchArrays(As, Bs, Cs, alphas, betas)
         cfg_arr = None
         if cfgs is not None:
             cfg_arr = (Cfg * len(cfgs))(*[c if isinstance(c, Cfg) else Cfg(*c) for c in cfgs])
