@@ -106,7 +106,8 @@ MGEMM_API int32_t gemm(int64_t m, int64_t n, int64_t k, double alpha,
  *
  * Split-k (MGEMM_F64, cfg == NULL only): when the chosen tile leaves fewer than
  * about four work-groups per compute unit and k >= 512, k is cut into S <= 16
- * ranges (multiples of 256); their partial products go to the library-owned
+ * ranges (multiples of 256; computed with the three-stage 128 x 128 tile where its
+ * requirements hold and it fills the GPU); their partial products go to the library-owned
  * device workspace (S*m*n*8 bytes, grown on demand, MGEMM_ERR_NOMEM if it
  * cannot be, kept until mgemm_release_workspace(); calls on one device that use
  * it are ordered through it) and one kernel adds them in range order and applies

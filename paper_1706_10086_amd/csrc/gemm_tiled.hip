@@ -524,23 +524,19 @@ struct PipeShape {
     static constexpr int EPU = 16 / (int)sizeof(T);                // elements per unit
 };
 
+// One BM x BN tile (tm, tn) of C: the three-stage k-loop and the epilogue; lds
+// holds the three stages.
 template <typename T, int BM, int BN, int BK, int WGM, int WGN>
-__global__ void __launch_bounds__(64 * WGM * WGN)
-    __attribute__((amdgpu_waves_per_eu(WGM * WGN / 4))) gemm_pipe_kernel(GemmArgs p) {
+__device__ __forceinline__ void pipe_tile(const GemmArgs &p, u32x4_t *lds, int tm, int tn) {
     typedef PipeShape<T, BM, BN, BK, WGM, WGN> S;
     typedef Elem<T> E;
     typedef typename E::vec2 vec2;
     typedef typename E::acc4 acc4;
     static_assert(S::WM % 16 == 0 && S::WN % 16 == 0 && BK % 8 == 0, "tile shape");
-    __shared__ u32x4_t lds[3 * S::STAGE];
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wm = wave / WGN, wn = wave % WGN;
-    const int tiles_m = (int)((p.m + BM - 1) / BM);
-    const int tiles_n = (int)((p.n + BN - 1) / BN);
-    int tm, tn;
-    tile_of_block(blockIdx.x, gridDim.x, tiles_m, tiles_n, tm, tn);
     const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
     const T *__restrict__ A = (const T *)p.A;
     const T *__restrict__ B = (const T *)p.B;
@@ -744,6 +740,44 @@ __global__ void __launch_bounds__(64 * WGM * WGN)
         }
 }
 
+template <typename T, int BM, int BN, int BK, int WGM, int WGN>
+__global__ void __launch_bounds__(64 * WGM * WGN)
+    __attribute__((amdgpu_waves_per_eu(WGM * WGN / 4))) gemm_pipe_kernel(GemmArgs p) {
+    typedef PipeShape<T, BM, BN, BK, WGM, WGN> S;
+    __shared__ u32x4_t lds[3 * S::STAGE];
+    const int tiles_m = (int)((p.m + BM - 1) / BM);
+    const int tiles_n = (int)((p.n + BN - 1) / BN);
+    int tm, tn;
+    tile_of_block(blockIdx.x, gridDim.x, tiles_m, tiles_n, tm, tn);
+    pipe_tile<T, BM, BN, BK, WGM, WGN>(p, lds, tm, tn);
+}
+
+// Split-k with the three-stage tile: work-group (x, y) computes C tile x over
+// the y-th range of kc values of k (a multiple of BK, so A and B keep their
+// 16-byte alignment) with alpha = 1 and beta = 0 into plane y of W (m x n, row
+// stride n); splitk_reduce_kernel sums the planes.
+template <typename T, int BM, int BN, int BK, int WGM, int WGN>
+__global__ void __launch_bounds__(64 * WGM * WGN)
+    __attribute__((amdgpu_waves_per_eu(WGM * WGN / 4)))
+    gemm_pipe_splitk_kernel(GemmArgs p, int64_t kc, T *W) {
+    typedef PipeShape<T, BM, BN, BK, WGM, WGN> S;
+    __shared__ u32x4_t lds[3 * S::STAGE];
+    const int tiles_m = (int)((p.m + BM - 1) / BM);
+    const int tiles_n = (int)((p.n + BN - 1) / BN);
+    int tm, tn;
+    tile_of_block(blockIdx.x, gridDim.x, tiles_m, tiles_n, tm, tn);
+    const int64_t y = blockIdx.y, k0 = y * kc;
+    GemmArgs q = p;
+    q.k = p.k - k0 < kc ? p.k - k0 : kc;
+    q.A = (const T *)p.A + k0;
+    q.B = (const T *)p.B + k0 * p.ldb;
+    q.alpha = 1.0;
+    q.beta = 0.0;
+    q.C = W + y * p.m * p.n;
+    q.ldc = p.n;
+    pipe_tile<T, BM, BN, BK, WGM, WGN>(q, lds, tm, tn);
+}
+
 // ---------------------------------------------------------------------------
 // Launchers and registries.
 // ---------------------------------------------------------------------------
@@ -767,6 +801,26 @@ hipError_t launch_splitk(const GemmArgs &a, int S, int64_t kc, void *W, hipStrea
     hipLaunchKernelGGL((gemm_splitk_kernel<T, BM, BN, BK, WGM, WGN, EPT, DBUF, OCC, ALIGN>),
                        dim3((unsigned)blocks, (unsigned)S), dim3(64 * WGM * WGN), 0, s, a, kc,
                        (T *)W);
+    return hipGetLastError();
+}
+
+// FP64 split-k with the three-stage 128 x 128 x 16 eight-wave tile: its
+// requirements are those of launch_pipe (16-byte rows and bases, 32-bit panel
+// offsets); false if they do not hold.
+bool pipe_splitk_f64_eligible(const GemmArgs &a) {
+    constexpr int64_t EPU = 2, BM = 128, BK = 16, BN = 128;
+    return a.k >= 1 && a.n >= EPU && a.n % EPU == 0 && a.lda % EPU == 0 && a.ldb % EPU == 0 &&
+           ((uintptr_t)a.A % 16) == 0 && ((uintptr_t)a.B % 16) == 0 &&
+           BM * a.lda * 8 < ((int64_t)1 << 31) && (BK * a.ldb + BN) * 8 < ((int64_t)1 << 31);
+}
+
+hipError_t launch_pipe_splitk_f64(const GemmArgs &a, int S, int64_t kc, void *W, hipStream_t s) {
+    if (!pipe_splitk_f64_eligible(a)) return hipErrorInvalidValue;
+    const int64_t blocks = ((a.m + 127) / 128) * ((a.n + 127) / 128);
+    if (blocks <= 0) return hipSuccess;
+    if (blocks > 0x7fffffff || S < 1 || S > 65535) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL((gemm_pipe_splitk_kernel<double, 128, 128, 16, 4, 2>),
+                       dim3((unsigned)blocks, (unsigned)S), dim3(512), 0, s, a, kc, (double *)W);
     return hipGetLastError();
 }
 

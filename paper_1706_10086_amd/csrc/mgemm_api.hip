@@ -194,12 +194,15 @@ const KernelEntry *choose_entry(int32_t dtype, int64_t m, int64_t n, const mgemm
 
 int32_t split_gemm(const GemmArgs &a, int32_t dtype, hipStream_t s);
 
-// Split-k for the built-in choice: when the chosen tile (one with a split-k
-// kernel) leaves fewer than about four work-groups per compute unit, k is cut
-// into S ranges of at least SPLITK_MIN_K (a multiple of every tile's BK) so that
-// about four run per compute unit; the S partial products go to the library
-// workspace and one reduction kernel adds them in order and applies alpha and
-// beta.
+// Split-k for the built-in FP64 choice: when the chosen tile leaves fewer than
+// about four work-groups per compute unit, k is cut into S ranges of kc values (a
+// multiple of SPLITK_MIN_K, itself a multiple of every tile's BK; the last range
+// is the short one); the S partial products go to the library workspace and one
+// reduction kernel adds them in order and applies alpha and beta.  The ranges run
+// on the three-stage 128 x 128 tile (one work-group per compute unit) when that
+// fills at least three quarters of the compute units in one round, else on the
+// chosen two-stage tile (64 x 64 or 32 x 32) with about four work-groups per
+// compute unit.
 constexpr int64_t SPLITK_MIN_K = 256;
 constexpr int SPLITK_MAX = 16;
 
@@ -216,25 +219,49 @@ static int compute_units() {
     return cached[dev];
 }
 
-static int splitk_factor(int64_t m, int64_t n, int64_t k, const mgemm_cfg &c) {
-    const int cus = compute_units();
-    const int64_t tiles = tiles_of(m, n, c);
-    if (cus <= 0 || tiles <= 0) return 1;
-    int64_t S = (4 * (int64_t)cus + tiles - 1) / tiles;
-    S = std::min<int64_t>(S, k / SPLITK_MIN_K);
-    S = std::min<int64_t>(S, SPLITK_MAX);
-    return S > 1 ? (int)S : 1;
+struct SplitPlan {
+    int S = 1;              // number of k ranges (1: no split)
+    int64_t kc = 0;         // k per range
+    bool pipe = false;      // three-stage 128 x 128 tile
+};
+
+// S ranges wanted -> the ranges actually cut (kc rounded up to SPLITK_MIN_K)
+static void cut_k(int64_t k, int64_t want, SplitPlan &sp) {
+    want = std::min<int64_t>(std::min<int64_t>(want, k / SPLITK_MIN_K), SPLITK_MAX);
+    if (want < 2) return;
+    const int64_t kc = ((k + want - 1) / want + SPLITK_MIN_K - 1) / SPLITK_MIN_K * SPLITK_MIN_K;
+    const int64_t S = (k + kc - 1) / kc;
+    if (S < 2) return;
+    sp.S = (int)S;
+    sp.kc = kc;
 }
 
-static int32_t run_splitk(const KernelEntry *e, const GemmArgs &a, int32_t dtype, bool al, int S,
-                          hipStream_t s) {
-    // k per range: a multiple of SPLITK_MIN_K, so that the last range is the short one
-    const int64_t kc = ((a.k + S - 1) / S + SPLITK_MIN_K - 1) / SPLITK_MIN_K * SPLITK_MIN_K;
-    S = (int)((a.k + kc - 1) / kc);
+static SplitPlan splitk_plan(const GemmArgs &a, const KernelEntry *e) {
+    SplitPlan sp;
+    const int cus = compute_units();
+    const int64_t tiles = tiles_of(a.m, a.n, e->cfg);
+    if (cus <= 0 || tiles <= 0 || !e->splitk[0]) return sp;
+    if ((4 * (int64_t)cus + tiles - 1) / tiles < 2) return sp;       // enough tiles already
+    if (pipe_splitk_f64_eligible(a)) {
+        const int64_t t128 = ((a.m + 127) / 128) * ((a.n + 127) / 128);
+        SplitPlan pp;
+        cut_k(a.k, cus / t128, pp);
+        if (pp.S > 1 && 4 * t128 * pp.S >= 3 * (int64_t)cus) {
+            pp.pipe = true;
+            return pp;
+        }
+    }
+    cut_k(a.k, (4 * (int64_t)cus + tiles - 1) / tiles, sp);
+    return sp;
+}
+
+static int32_t run_splitk(const KernelEntry *e, const GemmArgs &a, int32_t dtype, bool al,
+                          const SplitPlan &sp, hipStream_t s) {
     const size_t es = dtype == MGEMM_F32 ? 4 : 8;
-    return with_workspace((size_t)S * a.m * a.n * es, s, [&](uint8_t *W) -> int32_t {
-        hipError_t he = e->splitk[al ? 0 : 1](a, S, kc, W, s);
-        if (he == hipSuccess) he = splitk_reduce(dtype, W, S, a, s);
+    return with_workspace((size_t)sp.S * a.m * a.n * es, s, [&](uint8_t *W) -> int32_t {
+        hipError_t he = sp.pipe ? launch_pipe_splitk_f64(a, sp.S, sp.kc, W, s)
+                                : e->splitk[al ? 0 : 1](a, sp.S, sp.kc, W, s);
+        if (he == hipSuccess) he = splitk_reduce(dtype, W, sp.S, a, s);
         return he == hipSuccess ? 0 : hip_error(he, "split-k launch");
     });
 }
@@ -266,8 +293,8 @@ int32_t gemm_ex(int64_t m, int64_t n, int64_t k, double alpha, const void *A, in
     if (!e) return err;
     const bool al = rows_aligned(A, lda, B, ldb, dtype);
     if (!cfg && e->splitk[0]) {
-        const int S = splitk_factor(m, n, k, e->cfg);
-        if (S > 1) return run_splitk(e, a, dtype, al, S, s);
+        const SplitPlan sp = splitk_plan(a, e);
+        if (sp.S > 1) return run_splitk(e, a, dtype, al, sp, s);
     }
     hipError_t he = (al ? e->launch : e->launch_unaligned)(a, s);
     if (he != hipSuccess) return hip_error(he, "gemm launch");

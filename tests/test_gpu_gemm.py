@@ -175,8 +175,11 @@ def test_fp32_within_gamma_bound(dev, orc):
         assert err < 1e-6
 
 
-SPLITK_SHAPES = [(1024, 1024, 1024), (1000, 999, 3001), (37, 45, 5000), (64, 1024, 777),
-                 (1, 1, 70000), (300, 200, 600), (511, 130, 513)]
+# the first four take the three-stage 128 x 128 tile for the k ranges (the last
+# with a ragged final range: 512 + 512 + 76), the others the 64 x 64 or 32 x 32 tile
+SPLITK_SHAPES = [(1024, 1024, 1024), (896, 1024, 1536), (1024, 512, 4096), (1024, 1024, 1100),
+                 (1000, 999, 3001), (37, 45, 5000), (64, 1024, 777), (1, 1, 70000),
+                 (300, 200, 600), (511, 130, 513)]
 
 
 @pytest.mark.parametrize("dtype", [mg.F64])
@@ -215,6 +218,21 @@ def test_split_k_default_choice(dev, orc, dtype):
     whole = run_gemm(dev, A, B, np.zeros((n, n)), 1.0, 0.0, dtype=dtype, cfg=whole_cfg)
     assert not np.array_equal(split, whole)
     assert np.linalg.norm(split - whole) <= 4 * n * u * np.linalg.norm(whole)
+    # the same k ranges on the two-stage tile (an odd leading dimension of A rules
+    # out the three-stage kernel): every tile sums a range in the same order, so
+    # both splits agree bit for bit
+    for k in (1024, 1100):
+        A = synth.uniform_pm1((n, k), 33 + k)
+        B = synth.uniform_pm1((k, n), 34 + k)
+        tA, tB = to_dev(A, dev), to_dev(B, dev)
+        tC1 = torch.zeros((n, n), device=dev, dtype=torch.float64)
+        mg.gemm(tA, tB, tC1, 1.0, 0.0)
+        pad = torch.full((n, k + 1), float("nan"), device=dev, dtype=torch.float64)
+        pad[:, :k] = tA
+        tC2 = torch.zeros((n, n), device=dev, dtype=torch.float64)
+        mg.gemm(pad[:, :k], tB, tC2, 1.0, 0.0)
+        torch.cuda.synchronize()
+        assert torch.equal(tC1, tC2), k
 
 
 def test_run_to_run_determinism(dev):
