@@ -43,7 +43,7 @@ PEAK_INT8_TOPS = 5033.2
 # Measured HBM traffic of the N = 8192 FP64 launch (FETCH_SIZE x 2.0 + WRITE_SIZE x
 # 1.0, the factors a plain copy of known size gives); valid for the kernel as
 # profiled -- to be re-measured whenever the FP64 tile kernel changes.
-TRAFFIC_F64_N8192 = 21.56e9
+TRAFFIC_F64_N8192 = 21.22e9
 
 
 def parse():
