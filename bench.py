@@ -35,8 +35,12 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+from paper_1706_10086_amd import perfmodel as pm  # noqa: E402  (closed forms, Eq. 2-8)
+
 METRIC = "GEMM TFLOP/s (% peak): FP64 vs split-precision at equal error; tuner regret"
-PEAK_F64_TFLOPS = 78.6       # MI355X FP64 matrix peak (published)
+# MI355X dense matrix peaks (published; Eq. 8 with 256 CUs at 2.4 GHz gives the same
+# to 0.1 %, perfmodel.mi355x_peak)
+PEAK_F64_TFLOPS = 78.6
 PEAK_F32_TFLOPS = 157.3
 PEAK_BF16_TFLOPS = 2516.6
 PEAK_INT8_TOPS = 5033.2
@@ -241,7 +245,7 @@ def leg_batched(mg, torch, dev, plan_only=False):
     As = [views[3 * i].view(int(m), int(k)) for i, (m, k) in enumerate(zip(ms, ks))]
     Bs = [views[3 * i + 1].view(int(k), int(n)) for i, (k, n) in enumerate(zip(ks, ns))]
     Cs = [views[3 * i + 2].view(int(m), int(n)) for i, (m, n) in enumerate(zip(ms, ns))]
-    flops = float(sum(2.0 * m * n * k for m, n, k in zip(ms, ns, ks)))
+    flops = float(sum(pm.gemm_flops(m, n, k) for m, n, k in zip(ms, ns, ks)))
     stream = torch.cuda.current_stream()
     plan = mg.BatchedPlan(As, Bs, Cs, 1.0, 0.0, stream=stream)
     tp = timed(plan.execute, stream, 10, warmup=2)
@@ -255,11 +259,15 @@ def leg_batched(mg, torch, dev, plan_only=False):
         log("bench: FP64 per-problem launches timed")
     nbytes = float(sum(8.0 * (m * k + k * n + m * n) for m, n, k in zip(ms, ns, ks)))
     gms = float(np.mean(tp))
+    # the batch's time bound problem by problem: sum over problems of max(F / peak, B / BW)
+    bound_s = float(sum(max(pm.gemm_flops(m, n, k) / (PEAK_F64_TFLOPS * 1e12),
+                            8.0 * (m * k + k * n + m * n) / 8e12) for m, n, k in zip(ms, ns, ks)))
     out = {"problems": cnt, "flops": flops, "bytes": nbytes, "buckets": info["buckets"],
            "tiles": info["tiles"], "graph_ms": round(gms, 4),
            "graph_tflops": round(flops / gms / 1e9, 3),
            # max(sum F / peak, sum B / bandwidth) / t: the batch's roofline fraction
            "roofline_frac": round(max(flops / (PEAK_F64_TFLOPS * 1e12), nbytes / 8e12) / (gms * 1e-3), 4),
+           "roofline_frac_per_problem": round(bound_s / (gms * 1e-3), 4),
            "per_problem_ms": None if plan_only else round(float(np.mean(tl)), 4),
            "per_problem_tflops": None if plan_only else round(flops / float(np.mean(tl)) / 1e9, 3),
            "speedup": None if plan_only else round(float(np.mean(tl)) / gms, 3)}
@@ -411,7 +419,7 @@ def main():
     per = [ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)]
     total_ms = ev[0].elapsed_time(ev[-1])
     ms = total_ms / args.steps
-    flops = 2.0 * n ** 3
+    flops = pm.gemm_flops(n, n, n)
     tflops = flops / (ms * 1e-3) / 1e12
     kern_ms = float(np.mean(per))
     best_ms = float(np.min(per))
@@ -469,7 +477,11 @@ def main():
                      "kernel": "gemm_pipe_kernel<double,256,128,16,4,2> "
                                "(one launch per step)",
                      "kernel_avg_ms": round(kern_ms, 4),
-                     "work_per_launch": f"2*N^3 = {flops:.4g} FLOP"},
+                     "work_per_launch": f"2*N^3 = {flops:.4g} FLOP",
+                     # Eq. 6 for the kernel's 256 x 128 tiles: the bytes with no cache
+                     # reuse, against the algorithmic minimum (A, B, C read, C written)
+                     "traffic_model": {"tiles_no_reuse": pm.tile_traffic_bytes(n, n, n, 256, 128, 8),
+                                       "algorithmic": 4.0 * 8 * n * n}},
         "cpu_baseline": cpu,
     }
     if not args.no_extras:
