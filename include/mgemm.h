@@ -263,10 +263,11 @@ MGEMM_API int32_t mgemm_probe_mfma(int32_t dtype, const void *A, const void *B, 
 /* Diagnostic: one low-precision matrix-core step with operand and accumulator
  * registers passed unchanged per lane, to pin the lane layouts the split path
  * relies on.  kind 0: bf16 32x32x16 (float out), 1: int8 32x32x32 (int32 out),
- * 2: bf16 16x16x32, 3: int8 16x16x64.  a, b: 64 x 16 bytes of device memory (the
- * 16-byte operand of lane l at byte 16 l); d: 64 x 16 32-bit words (accumulator
- * element r of lane l at word 16 l + r; 4 elements for kinds 2, 3).  Returns 0,
- * -1 (kind) or -2 (NULL buffer). */
+ * 2: bf16 16x16x32, 3: int8 16x16x64, 4: FP8 e4m3 32x32x64 (float out).  a, b:
+ * 64 x 16 bytes of device memory (the 16-byte operand of lane l at byte 16 l; for
+ * kind 4 64 x 32 bytes, the 32-byte operand of lane l at byte 32 l); d: 64 x 16
+ * 32-bit words (accumulator element r of lane l at word 16 l + r; 4 elements for
+ * kinds 2, 3).  Returns 0, -1 (kind) or -2 (NULL buffer). */
 MGEMM_API int32_t mgemm_probe_mfma_raw(int32_t kind, const void *a, const void *b, void *d,
                                        void *stream);
 

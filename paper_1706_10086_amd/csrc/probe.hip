@@ -56,15 +56,29 @@ extern "C" int32_t mgemm_probe_mfma(int32_t dtype, const void *A, const void *B,
 //   kind 1: v_mfma_i32_32x32x32_i8    a, b: 16 int8 per lane; d: 16 int32 per lane
 //   kind 2: v_mfma_f32_16x16x32_bf16  a, b: 8 bf16 per lane;  d: 4 float per lane
 //   kind 3: v_mfma_i32_16x16x64_i8    a, b: 16 int8 per lane; d: 4 int32 per lane
+//   kind 4: v_mfma_f32_32x32x64_f8f6f4 with both operands FP8 e4m3 (no block
+//           scaling)                    a, b: 32 e4m3 per lane; d: 16 float per lane
 // ---------------------------------------------------------------------------
 namespace mgemm {
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef float v16f __attribute__((ext_vector_type(16)));
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
+typedef int v8i __attribute__((ext_vector_type(8)));
 
 __global__ void probe_raw_kernel(int kind, const uint4 *a, const uint4 *b, uint32_t *d) {
     const int l = threadIdx.x;
+    if (kind == 4) {
+        const v4i a0 = __builtin_bit_cast(v4i, a[2 * l]), a1 = __builtin_bit_cast(v4i, a[2 * l + 1]);
+        const v4i b0 = __builtin_bit_cast(v4i, b[2 * l]), b1 = __builtin_bit_cast(v4i, b[2 * l + 1]);
+        const v8i va = {a0[0], a0[1], a0[2], a0[3], a1[0], a1[1], a1[2], a1[3]};
+        const v8i vb = {b0[0], b0[1], b0[2], b0[3], b1[0], b1[1], b1[2], b1[3]};
+        v16f acc = {};
+        // format codes 0, 0: e4m3 operands; scales 0: the unscaled instruction
+        acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(va, vb, acc, 0, 0, 0, 0, 0, 0);
+        for (int r = 0; r < 16; ++r) d[l * 16 + r] = __float_as_uint(acc[r]);
+        return;
+    }
     const uint4 ua = a[l], ub = b[l];
     if (kind == 0) {
         v16f acc = {};
@@ -90,11 +104,11 @@ __global__ void probe_raw_kernel(int kind, const uint4 *a, const uint4 *b, uint3
 }
 }  // namespace mgemm
 
-// a, b: 64 x 16 bytes (one 16-byte operand register group per lane); d: 64 x 16
-// 32-bit words (accumulator element r of lane l at d[16 l + r]).
+// a, b: 64 x 16 bytes (one 16-byte operand register group per lane; 64 x 32 for
+// kind 4); d: 64 x 16 32-bit words (accumulator element r of lane l at d[16 l + r]).
 extern "C" int32_t mgemm_probe_mfma_raw(int32_t kind, const void *a, const void *b, void *d,
                                         void *stream) {
-    if (kind < 0 || kind > 3) return mgemm::set_error(-1, "kind must be 0..3");
+    if (kind < 0 || kind > 4) return mgemm::set_error(-1, "kind must be 0..4");
     if (!a || !b || !d) return mgemm::set_error(-2, "NULL buffer");
     hipLaunchKernelGGL(mgemm::probe_raw_kernel, dim3(1), dim3(64), 0, (hipStream_t)stream, kind,
                        (const uint4 *)a, (const uint4 *)b, (uint32_t *)d);
