@@ -43,6 +43,7 @@ METRIC = "GEMM TFLOP/s (% peak): FP64 vs split-precision at equal error; tuner r
 PEAK_F64_TFLOPS = 78.6
 PEAK_F32_TFLOPS = 157.3
 PEAK_BF16_TFLOPS = 2516.6
+PEAK_FP8_TFLOPS = 5033.2
 PEAK_INT8_TOPS = 5033.2
 # Measured HBM traffic of the N = 8192 FP64 launch (FETCH_SIZE x 2.0 + WRITE_SIZE x
 # 1.0, the factors a plain copy of known size gives); valid for the kernel as
@@ -128,8 +129,8 @@ def leg_split(mg, torch, dev, n=8192, with_small=True):
     ref = oracle.gemm_dot2(1.0, A[rows], B, nthreads=oracle.num_procs())
     out = {"n": n, "inputs": "u*2^e, u uniform[-1,1], e uniform integer in [-20,20]",
            "error": f"normwise vs double-double oracle on {len(rows)} sampled rows"}
-    for name, dt in (("f64", mg.F64), ("bf16", mg.SPLIT_BF16), ("int8", mg.SPLIT_INT8),
-                     ("crt_int8", mg.CRT_INT8)):
+    for name, dt in (("f64", mg.F64), ("bf16", mg.SPLIT_BF16), ("fp8", mg.SPLIT_FP8),
+                     ("int8", mg.SPLIT_INT8), ("crt_int8", mg.CRT_INT8)):
         ts = timed(lambda: mg.gemm(tA, tB, tC, 1.0, 0.0, dtype=dt, stream=stream), stream, 5)
         got = tC[torch.from_numpy(rows).to(dev)].cpu().numpy()
         err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
@@ -139,6 +140,7 @@ def leg_split(mg, torch, dev, n=8192, with_small=True):
                      "rel_err": err}
         log(f"  {name}: {ms:.3f} ms, err {err:.2e}")
     out["bf16"]["mfma_util"] = round(21 * 2.0 * n ** 3 / (out["bf16"]["ms"] * 1e9) / PEAK_BF16_TFLOPS, 4)
+    out["fp8"]["mfma_util"] = round(66 * 2.0 * n ** 3 / (out["fp8"]["ms"] * 1e9) / PEAK_FP8_TFLOPS, 4)
     out["int8"]["mfma_util"] = round(36 * 2.0 * n ** 3 / (out["int8"]["ms"] * 1e9) / PEAK_INT8_TOPS, 4)
     # 16 int8 GEMMs of the zero-padded operands (one per modulus)
     npad = -(-n // 256) * 256
@@ -159,8 +161,8 @@ def leg_split(mg, torch, dev, n=8192, with_small=True):
     rows = np.array([0, 1, 1000, 2222, 3000, m - 1])
     ref = oracle.gemm_dot2(1.0, A[rows], B, nthreads=oracle.num_procs())
     small = {"n": m}
-    for name, dt in (("f64", mg.F64), ("bf16", mg.SPLIT_BF16), ("int8", mg.SPLIT_INT8),
-                     ("crt_int8", mg.CRT_INT8)):
+    for name, dt in (("f64", mg.F64), ("bf16", mg.SPLIT_BF16), ("fp8", mg.SPLIT_FP8),
+                     ("int8", mg.SPLIT_INT8), ("crt_int8", mg.CRT_INT8)):
         ts = timed(lambda: mg.gemm(tA, tB, tC, 1.0, 0.0, dtype=dt, stream=stream), stream, 5)
         got = tC[torch.from_numpy(rows).to(dev)].cpu().numpy()
         ms = float(np.mean(ts))

@@ -18,11 +18,11 @@
  *          (batched plans keep them until destroyed, see below).  C must not
  *          overlap A or B.
  * Types    MGEMM_F64: A, B, C are double.  MGEMM_F32: float (alpha, beta are
- *          rounded to float).  MGEMM_SPLIT_BF16 / MGEMM_SPLIT_INT8: A, B, C are
- *          double; the product is emulated from bfloat16 (6 slices, 21 slice
- *          pairs) / int8 (8 slices, 36 pairs) slices of A and B (Ozaki scheme),
- *          see gemm_ex.  MGEMM_SPLIT_FP8 (e4m3 slices) is reserved and returns
- *          MGEMM_ERR_NOCONFIG.  MGEMM_CRT_INT8: A, B, C are double; the product
+ *          rounded to float).  MGEMM_SPLIT_BF16 / MGEMM_SPLIT_FP8 /
+ *          MGEMM_SPLIT_INT8: A, B, C are double; the product is emulated from
+ *          bfloat16 (6 slices, 21 slice pairs) / FP8 e4m3 (11 slices, 66 pairs) /
+ *          int8 (8 slices, 36 pairs) slices of A and B (Ozaki scheme), see
+ *          gemm_ex.  MGEMM_CRT_INT8: A, B, C are double; the product
  *          is emulated from int8 residues of A and B modulo 16 coprime moduli
  *          (Ozaki scheme II), see gemm_ex.
  * Stream   Work is enqueued on the given HIP stream (NULL: the stream set with
@@ -117,10 +117,12 @@ MGEMM_API int32_t gemm(int64_t m, int64_t n, int64_t k, double alpha,
  * Split dtypes: A and B are scaled per row / column by powers of two, sliced
  * into small integers and multiplied on matrix cores with exact accumulation;
  * the kept slice-pair products (s + t <= S + 1) are summed exactly and rounded
- * once to FP64, then C = alpha*v + beta*C.  For k above 131072 (bf16) or 16384
- * (int8) the k-range is processed in passes, each rounded once.  The slices live
- * in a library-owned device workspace (about 2*S*bytes*(m+n)*k) that grows on
- * demand (MGEMM_ERR_NOMEM if it cannot) and is kept until
+ * once to FP64, then C = alpha*v + beta*C.  For k above 131072 (bf16, FP8) or
+ * 16384 (int8) the k-range is processed in passes, each rounded once.  The slices
+ * live in a library-owned device workspace (about 2*S*bytes*(m+n)*k, plus 16
+ * bytes per element of C for FP8) that grows on demand (MGEMM_ERR_NOMEM if it
+ * cannot; MGEMM_ERR_NOCONFIG if the int8 or FP8 slices of one operand pass 4 GiB)
+ * and is kept until
  * mgemm_release_workspace() or unload.  The call waits once for the scaling
  * step on the stream (to report MGEMM_ERR_NONFINITE before C is touched);
  * split calls on one device are ordered through the shared workspace. cfg must

@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(HERE, "libmgemm.so")
 F64, F32, SPLIT_BF16, SPLIT_FP8, SPLIT_INT8, CRT_INT8 = 0, 1, 2, 3, 4, 5
 DTYPE_NAMES = {F64: "f64", F32: "f32", SPLIT_BF16: "split_bf16", SPLIT_FP8: "split_fp8",
                SPLIT_INT8: "split_int8", CRT_INT8: "crt_int8"}
-SPLIT_SLICES = {SPLIT_BF16: 6, SPLIT_INT8: 8}
+SPLIT_SLICES = {SPLIT_BF16: 6, SPLIT_FP8: 11, SPLIT_INT8: 8}
 ERR_HIP, ERR_NOMEM, ERR_NONFINITE, ERR_NOCONFIG, ERR_PLAN = 1, 2, 3, 4, 5
 
 # Every symbol include/mgemm.h declares.

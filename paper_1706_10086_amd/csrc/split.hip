@@ -16,11 +16,13 @@
 //              sums are exact: bf16 products accumulate in FP32 in chunks small
 //              enough that every partial sum is an integer below 2^24 and are then
 //              added into two FP64 accumulators that hold exact integers (levels
-//              2-4 and 5-7); int8 products accumulate exactly in int32.
+//              2-4 and 5-7; FP8: 2-6 and 7-12); int8 products accumulate exactly in
+//              int32.
 //  4. combine  the exact sum of the kept levels is rounded once to FP64,
 //              scaled by 2^(e_i + f_j) and the epilogue alpha*v + beta*C applied.
 //
 // Formats: bf16 slices, b1 = 8, b = 9 bits, round to nearest, S = 6 (21 pairs);
+//          FP8 e4m3 slices, b1 = 4, b = 5 bits, round to nearest, S = 11 (66 pairs);
 //          int8 slices, b1 = b = 7 bits, round toward zero, S = 8 (36 pairs).
 //
 // Workspace (device, owned by the library, grown on demand): exponents, a
@@ -68,6 +70,23 @@ struct FmtI8 {
     static constexpr int KC = 32;
     static constexpr int ELEM = 1;
     static __device__ inline uint32_t encode(double q) { return (uint32_t)(uint8_t)(int8_t)(int)q; }
+};
+
+struct FmtE4M3 {
+    static constexpr int S = 11;
+    static constexpr int B1 = 4;
+    static constexpr int B = 5;
+    static constexpr bool NEAREST = true;
+    static constexpr int KC = 64;       // k of one FP8 MFMA step
+    static constexpr int ELEM = 1;
+    // integer-valued q with |q| <= 16 -> FP8 e4m3 byte (OCP: exponent bias 7, three
+    // mantissa bits; exact, at most 4 significant bits)
+    static __device__ inline uint32_t encode(double q) {
+        if (q == 0.0) return 0u;
+        const uint32_t f = __float_as_uint((float)q);
+        const uint32_t ex = ((f >> 23) & 0xFFu) - 127u + 7u;
+        return ((f >> 24) & 0x80u) | (ex << 3) | ((f >> 20) & 7u);
+    }
 };
 
 // bytes of one (row, k-chunk) run: all S slices of KC elements
@@ -265,6 +284,7 @@ struct PairArgs {
     int64_t ch0, ch1;   // chunk range of this pass
     double alpha, beta;
     int tiles_m, tiles_n;
+    double *sums;       // FP8 pair kernel: exact level sums, 32 per lane (else unused)
 };
 
 // 32x32 MFMA accumulator element r of lane l -> (row, column) in the wave block
@@ -703,6 +723,135 @@ split_pairs_bf16_pipe_kernel(PairArgs a) {
     }
 }
 
+// FP8 e4m3: 4 waves (2 x 2, one per SIMD) own a 64 x 64 tile of C, each wave a
+// 32 x 32 block held as one 32x32 FP32 accumulator per level (11 levels).  A
+// k-chunk (64 k) of all 11 slices of the tile's 64 A rows sits in one of two A
+// stages, of its 64 B columns in the one B stage.  At the start of a chunk every
+// wave copies its 11 B fragments into registers; once all have, the next chunk's
+// direct loads fill the B stage and the other A stage while the 66 products run,
+// the A fragments being read row by row from the current A stage.  Products are
+// at most 16 x 16 = 2^8, so each level's FP32 sum stays an exact integer below
+// 2^24 for 64 chunks (11 x 64 x 64 x 2^8 < 2^24); it is then added into the exact
+// FP64 sums hi (levels 2-6 in units of level 6) and lo (levels 7-12 in units of
+// level 12).  Slice buffers are addressed with 32-bit offsets (each below 4 GiB,
+// checked on the host).
+constexpr int E_BM = 64, E_BN = 64;
+constexpr int E_THREADS = 256;
+constexpr int E_UNITS = 44;                              // units of one row run (11 x 64 B)
+constexpr int E_SROW = 45;                               // padded LDS row (units)
+constexpr int E_AUNITS = E_BM * E_SROW;                  // 2880 units per A stage
+constexpr int E_BUNITS = E_BN * E_SROW;                  // 2880 units in the B stage
+constexpr int E_UNITS_CHUNK = E_AUNITS + E_BUNITS;       // units loaded per chunk
+constexpr int E_LOADS = (E_UNITS_CHUNK + E_THREADS - 1) / E_THREADS;   // 23 per lane
+constexpr int E_FLUSH = 64;                              // chunks between flushes
+static_assert(E_AUNITS % 64 == 0 && E_UNITS_CHUNK % 64 == 0, "a wave's loads lie in one operand");
+static_assert(11 * E_FLUSH * 64 * 256 < (1 << 24), "FP32 level sums stay exact");
+static_assert((2 * E_AUNITS + E_BUNITS) * 16 <= 163840, "LDS");
+
+typedef int v8i_t __attribute__((ext_vector_type(8)));
+
+__global__ void __launch_bounds__(E_THREADS) __attribute__((amdgpu_waves_per_eu(1, 1)))
+split_pairs_e4m3_kernel(PairArgs a) {
+    __shared__ u32x4 lds[2 * E_AUNITS + E_BUNITS];      // A stage 0, A stage 1, B stage
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = wave >> 1, wn = wave & 1;
+    int tm, tn;
+    tile_of_block(blockIdx.x, gridDim.x, a.tiles_m, a.tiles_n, tm, tn);
+    const int64_t m0 = (int64_t)tm * E_BM, n0 = (int64_t)tn * E_BN;
+    const int r32 = lane & 31, kh = lane >> 5;
+    // fragment of slice s: 32 bytes (units 4s + 2kh, +1) of the wave's row / column
+    const int a_off = (wm * 32 + r32) * E_SROW + 2 * kh;
+    const int b_off = 2 * E_AUNITS + (wn * 32 + r32) * E_SROW + 2 * kh;
+    const uint32_t stride = (uint32_t)a.nch * (uint32_t)(E_UNITS * 16);
+
+    // all loads of chunk ch: A rows into A stage ast, B columns into the B stage
+    // (the last instruction only for the waves whose units lie inside the chunk)
+    auto issue = [&](uint32_t ch, int ast) {
+#pragma unroll
+        for (int i = 0; i < E_LOADS; ++i) {
+            const int first = i * E_THREADS + wave * 64;          // uniform per wave
+            if (first >= E_UNITS_CHUNK) continue;
+            const bool in_a = first < E_AUNITS;
+            const int v = (in_a ? first : first - E_AUNITS) + lane;
+            const int row = v / E_SROW, c = v % E_SROW;
+            const uint32_t row0 = in_a ? (uint32_t)m0 : (uint32_t)n0;
+            const uint8_t *src = (in_a ? a.QA : a.QB) +
+                                 ((row0 + (uint32_t)row) * stride + ch * (uint32_t)(E_UNITS * 16) +
+                                  (uint32_t)(c < E_UNITS ? c : E_UNITS - 1) * 16u);
+            u32x4 *dst = in_a ? lds + ast * E_AUNITS + first : lds + 2 * E_AUNITS + (first - E_AUNITS);
+            __builtin_amdgcn_global_load_lds((const void *)src,
+                                             (__attribute__((address_space(3))) void *)dst, 16, 0, 0);
+        }
+    };
+    auto frag = [&](int off) {
+        const v4i x0 = __builtin_bit_cast(v4i, lds[off]), x1 = __builtin_bit_cast(v4i, lds[off + 1]);
+        return (v8i_t)__builtin_shufflevector(x0, x1, 0, 1, 2, 3, 4, 5, 6, 7);
+    };
+
+    v16f acc[11];
+#pragma unroll
+    for (int l = 0; l < 11; ++l) acc[l] = v16f{};
+    // this lane's exact sums in the workspace: hi r at sums[r * 64], lo r at
+    // sums[(16 + r) * 64] (lanes adjacent, so each access is one coalesced run)
+    double *sums = a.sums + ((int64_t)blockIdx.x * 4 + wave) * 32 * 64 + lane;
+#pragma unroll
+    for (int r = 0; r < 32; ++r) sums[r * 64] = 0.0;
+
+    // level lv (0-based: slices s + t = lv) into hi (lv <= 4, units of level 4) or
+    // lo (units of level 10); both stay exact integers below 2^53 within a pass
+    auto flush = [&]() {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            double hi = sums[r * 64], lo = sums[(16 + r) * 64];
+#pragma unroll
+            for (int lv = 0; lv < 11; ++lv) {
+                const double sc = (double)(1 << (5 * (lv < 5 ? 4 - lv : 10 - lv)));
+                if (lv < 5) hi = fma((double)acc[lv][r], sc, hi);
+                else lo = fma((double)acc[lv][r], sc, lo);
+            }
+            sums[r * 64] = hi;
+            sums[(16 + r) * 64] = lo;
+        }
+#pragma unroll
+        for (int lv = 0; lv < 11; ++lv) acc[lv] = v16f{};
+    };
+
+    const uint32_t c0 = (uint32_t)a.ch0, c1 = (uint32_t)a.ch1;
+    issue(c0, 0);
+    for (uint32_t c = c0; c < c1; ++c) {
+        const int ast = (int)((c - c0) & 1);
+        __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));          // own loads of chunk c landed
+        __syncthreads();                                  // everyone's
+        v8i_t fb[11];
+#pragma unroll
+        for (int t = 0; t < 11; ++t) fb[t] = frag(b_off + 4 * t);
+        __syncthreads();                                  // the B stage is free again
+        if (c + 1 < c1) issue(c + 1, ast ^ 1);
+        const int abase = ast * E_AUNITS + a_off;
+        v8i_t fa = frag(abase);
+#pragma unroll
+        for (int s = 0; s < 11; ++s) {
+            const v8i_t fcur = fa;
+            if (s + 1 < 11) fa = frag(abase + 4 * (s + 1));
+#pragma unroll
+            for (int t = 0; t + s < 11; ++t)
+                acc[s + t] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                    fcur, fb[t], acc[s + t], 0, 0, 0, 0, 0, 0);
+        }
+        if ((c - c0 + 1) % E_FLUSH == 0 || c + 1 == c1) flush();
+    }
+    __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+
+    // exact value = hi 2^-28 + lo 2^-58, rounded once
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const double v = fma(sums[r * 64], 0x1p-28, sums[(16 + r) * 64] * 0x1p-58);
+        store_c(a, m0 + wm * 32 + acc_row(lane, r), n0 + wn * 32 + r32, v);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Host side: workspace and driver.
 // ---------------------------------------------------------------------------
@@ -763,6 +912,7 @@ struct PairKernel {
     int tile_m, tile_n, threads;
     int kpad;         // k padded to a multiple of this (a multiple of KPAD)
     int chunk_mult;   // each pass covers a multiple of this many chunks
+    bool sums = false;  // needs PairArgs::sums (16 bytes per element of C)
 };
 
 constexpr int64_t SPLIT_PAD = 128;   // m and n padded to a multiple of every pair tile
@@ -775,7 +925,9 @@ static int32_t run_split(const GemmArgs &g, hipStream_t s, Workspace &w, int max
     const size_t a_bytes = (size_t)mp * kp * F::S * F::ELEM;
     const size_t b_bytes = (size_t)np * kp * F::S * F::ELEM;
     const size_t e_bytes = round_up(mp * 4, 256), f_bytes = round_up(np * 4, 256);
-    const size_t total = e_bytes + f_bytes + 256 + a_bytes + b_bytes;
+    // the FP8 pair kernel keeps its exact sums (16 bytes per element of C) here
+    const size_t s_bytes = pk.sums ? (size_t)mp * np * 16 : 0;
+    const size_t total = e_bytes + f_bytes + 256 + a_bytes + b_bytes + s_bytes;
     int32_t rc = ws_reserve(w, total);
     if (rc) return rc;
     int *e = (int *)w.base;
@@ -783,6 +935,7 @@ static int32_t run_split(const GemmArgs &g, hipStream_t s, Workspace &w, int max
     int *flag = (int *)(w.base + e_bytes + f_bytes);
     uint8_t *QA = w.base + e_bytes + f_bytes + 256;
     uint8_t *QB = QA + a_bytes;
+    double *sums = pk.sums ? (double *)(QB + b_bytes) : nullptr;
 
     hipError_t he = hipStreamWaitEvent(s, w.done, 0);
     if (he != hipSuccess) return set_error(MGEMM_ERR_HIP, "split: %s", hipGetErrorString(he));
@@ -825,6 +978,7 @@ static int32_t run_split(const GemmArgs &g, hipStream_t s, Workspace &w, int max
     pa.alpha = g.alpha;
     pa.tiles_m = (int)(mp / pk.tile_m);
     pa.tiles_n = (int)(np / pk.tile_n);
+    pa.sums = sums;
     const int64_t blocks = (int64_t)pa.tiles_m * pa.tiles_n;
     const int64_t pass_ch = max_pass_k / F::KC;
     // chunks holding data, rounded up to the kernel's multiple (zero slices)
@@ -908,6 +1062,16 @@ int32_t split_gemm(const GemmArgs &g, int32_t dtype, hipStream_t s) {
             return set_error(MGEMM_ERR_NOCONFIG, "split int8: slices of one operand exceed 4 GiB");
         return run_split<FmtI8>(g, s, w, 1 << 14,
                                 PairKernel{split_pairs_i8_pipe_kernel, Q_BM, Q_BN, 256, KPAD, 1});
+    }
+    if (dtype == MGEMM_SPLIT_FP8) {
+        // the pair kernel addresses each operand's slices with 32-bit offsets
+        const double big = (double)round_up(g.m > g.n ? g.m : g.n, SPLIT_PAD) *
+                           (double)round_up(g.k, KPAD) * FmtE4M3::S;
+        if (big >= 4294967296.0)
+            return set_error(MGEMM_ERR_NOCONFIG, "split fp8: slices of one operand exceed 4 GiB");
+        return run_split<FmtE4M3>(g, s, w, 1 << 17,
+                                  PairKernel{split_pairs_e4m3_kernel, E_BM, E_BN, E_THREADS, KPAD, 1,
+                                             true});
     }
     if (dtype == MGEMM_CRT_INT8) return run_crt(g, s, w);
     return set_error(MGEMM_ERR_NOCONFIG, "split dtype %d is not built", dtype);

@@ -1,7 +1,7 @@
 """GPU parity of the split-precision (Ozaki) emulated FP64 GEMM through the C ABI.
 
 The GPU path sums the kept slice-pair products exactly and rounds once, like the
-oracle's split model, so for k within one pass (131072 bf16 / 16384 int8) the
+oracle's split model, so for k within one pass (131072 bf16 and FP8 / 16384 int8) the
 results are compared BITWISE with the oracle on the same inputs; beyond that each
 pass rounds once and the comparison is normwise.  Accuracy against the
 double-double oracle: normwise relative error <= 1e-14 on the wide-range stress
@@ -16,8 +16,8 @@ pytestmark = pytest.mark.gpu
 
 import paper_1706_10086_amd as mg  # noqa: E402
 
-FMT = {mg.SPLIT_BF16: (0, 6), mg.SPLIT_INT8: (2, 8)}
-DTYPES = [mg.SPLIT_BF16, mg.SPLIT_INT8]
+FMT = {mg.SPLIT_BF16: (0, 6), mg.SPLIT_FP8: (1, 11), mg.SPLIT_INT8: (2, 8)}
+DTYPES = [mg.SPLIT_BF16, mg.SPLIT_FP8, mg.SPLIT_INT8]
 
 
 def say(*a):
@@ -83,6 +83,20 @@ def test_wide_range_1024_meets_1e14(dev, orc, dtype):
     say(f"  normwise err vs dot2 {err:.3e}")
     assert err <= 1e-14
     want = orc.split_gemm(1.0, A, B, fmt=fmt, S=S, nthreads=orc.num_procs())
+    assert np.array_equal(got, want)
+
+
+def test_fp8_level_flushes(dev, orc):
+    """k = 10000: 157 FP8 chunks of 64, so the FP32 level sums are flushed into the
+    exact FP64 sums twice before the final flush; bitwise equal to the oracle's
+    split model."""
+    m, n, k = 70, 90, 10000
+    say(f"split fp8 flush periods k={k}")
+    A = synth.wide_range((m, k), 4)
+    B = synth.wide_range((k, n), 5)
+    C = synth.uniform_pm1((m, n), 6)
+    got = gpu_split(dev, A, B, C, 0.75, -1.25, mg.SPLIT_FP8)
+    want = orc.split_gemm(0.75, A, B, -1.25, C, fmt=1, S=11, nthreads=orc.num_procs())
     assert np.array_equal(got, want)
 
 
@@ -198,7 +212,8 @@ def test_bf16_operands_beyond_4gib(dev, orc):
     """bf16 slices of A beyond 4 GiB (m = 16384, k = 24576: 12 bytes per element)
     take the register-staged pair kernel with 64-bit addresses: sampled rows
     bitwise equal to the oracle's split model.  int8 slices beyond 4 GiB are
-    refused with MGEMM_ERR_NOCONFIG before any operand is read."""
+    refused with MGEMM_ERR_NOCONFIG before any operand is read, and so are FP8
+    slices beyond 4 GiB."""
     m, n, k = 16384, 256, 24576
     say(f"split bf16 beyond 4 GiB: {(m, n, k)}, inputs on the device")
     g = torch.Generator(device=dev)
@@ -227,6 +242,10 @@ def test_bf16_operands_beyond_4gib(dev, orc):
     c = torch.zeros((16384, 8), device=dev, dtype=torch.float64)
     with pytest.raises(mg.MgemmError) as ei:
         mg.gemm(t, b, c, 1.0, 0.0, dtype=mg.SPLIT_INT8)
+    assert ei.value.code == mg.ERR_NOCONFIG
+    # FP8: 11 slices of one byte
+    with pytest.raises(mg.MgemmError) as ei:
+        mg.gemm(t, b, c, 1.0, 0.0, dtype=mg.SPLIT_FP8)
     assert ei.value.code == mg.ERR_NOCONFIG
     del t, b, c
     torch.cuda.empty_cache()
