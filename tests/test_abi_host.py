@@ -51,6 +51,7 @@ P = 1 << 20   # a fake, never dereferenced device address
     ((4, 4, 4, 1.0, P, 4, P * 4, 4, 0.0, P * 2, 4, 6), -12),
     # every emulated dtype is accepted: the bad leading dimension is reported
     ((4, 4, 8, 1.0, P, 7, P, 4, 0.0, P * 2, 4, 2), -6),
+    ((4, 4, 8, 1.0, P, 7, P, 4, 0.0, P * 2, 4, 3), -6),
     ((4, 4, 8, 1.0, P, 7, P, 4, 0.0, P * 2, 4, 4), -6),
     ((4, 4, 8, 1.0, P, 7, P, 4, 0.0, P * 2, 4, 5), -6),
     ((4, 4, 4, 1.0, P, 4, P * 4, 4, 0.0, P * 2, 4, -1), -12),
