@@ -5,9 +5,10 @@ exhaustive best.
 The procedure follows the paper's parameter tuning (Sec. 2.3 "Multidimensional
 parameter tuning" and Sec. 3, Tab. 4): a grid of tile parameters is searched,
 each point measured several times and the best kept, at a main size and checked
-at a control size.  Here the grid is the library's configuration registry
-(tile M/N/K, waves per work-group, elements per thread, double buffering,
-occupancy), the measurement is the device time of one gemm_ex call from HIP
+at a control size.  Here the grid searched is the library's configuration
+registry (tile M/N/K, waves per work-group, elements per thread, double
+buffering, occupancy), the compiled subset of the valid points of the raw grid
+defined below (``raw_grid``, ``grid_violations``); the measurement is the device time of one gemm_ex call from HIP
 events (warm-up, then ``reps`` timed runs; median and best kept), and a
 configuration whose first timed run is more than ``abandon`` times slower than
 the best so far for that shape is not measured further.
@@ -85,6 +86,72 @@ class DB:
 
 def flops(m, n, k) -> float:
     return 2.0 * m * n * k
+
+
+# The raw tuning grid (the paper's powers-of-two search of Sec. 2.3 and Tab. 4,
+# widened to the GPU's tile parameters): tile M/N/K, waves per work-group,
+# elements per thread, one or two LDS stages.  Every point is a kernel of its own
+# (tile shapes are template parameters), so the library compiles a subset: the
+# registry.  ``grid_violations`` is the filter that decides which points can be
+# compiled at all; the kernels' static assertions enforce the same rules.
+GRID_TILES = (32, 64, 128, 256)
+GRID_WAVES = (1, 2, 4, 8)
+GRID_EPT = (4, 8, 16)
+GRID_DBUF = (0, 1)
+# the registry also uses k-steps of 16 and runs of 2 elements (one 16-byte FP64
+# load): a 256 x 128 FP64 tile with three stages fits the LDS only at bk = 16
+EXT_BK = (16,)
+EXT_EPT = (2,)
+LDS_BYTES = 160 * 1024          # per compute unit
+ACC_VGPRS = 256                 # accumulator registers one lane may hold
+MFMA_TILE = 16                  # 16 x 16 output block of the FP64 and FP32 instructions
+
+
+def raw_grid():
+    """All 4^3 * 4 * 3 * 2 = 1536 points (bm, bn, bk, waves, ept, dbuf)."""
+    return [(bm, bn, bk, w, e, d) for bm in GRID_TILES for bn in GRID_TILES for bk in GRID_TILES
+            for w in GRID_WAVES for e in GRID_EPT for d in GRID_DBUF]
+
+
+def grid_violations(dtype: int, bm: int, bn: int, bk: int, waves: int, ept: int,
+                    dbuf: int) -> list:
+    """Names of the rules a configuration breaks (empty: it can be compiled).
+
+    * ``lds``:   the A and B stages, (bm bk + bk bn) S bytes each, fit in the LDS
+                 (``dbuf`` 0, 1, 2: one, two, three stages);
+    * ``acc``:   each lane's share of the bm x bn accumulators fits in 256 VGPRs;
+    * ``mfma``:  the waves split the tile into a WGM x WGN grid of wave tiles that
+                 are whole 16 x 16 instruction blocks;
+    * ``loads``: both slabs split into runs of ``ept`` consecutive elements, at
+                 least one per thread, each within one row of the slab.
+    """
+    S = 4 if dtype == F32 else 8
+    out = []
+    if (bm * bk + bk * bn) * S * (1 + dbuf) > LDS_BYTES:
+        out.append("lds")
+    if bm * bn * (S // 4) > ACC_VGPRS * 64 * waves:
+        out.append("acc")
+    if not any(waves % wgm == 0 and bm % (wgm * MFMA_TILE) == 0
+               and bn % ((waves // wgm) * MFMA_TILE) == 0 for wgm in GRID_WAVES if wgm <= waves):
+        out.append("mfma")
+    per_pass = 64 * waves * ept
+    if (bm * bk) % per_pass or (bk * bn) % per_pass or bm * bk < per_pass \
+            or bk * bn < per_pass or ept > bk or ept > bn or ept % 2:
+        out.append("loads")
+    return out
+
+
+def extended_grid():
+    """``raw_grid`` with k-steps of 16 and runs of 2 elements added (2560 points)."""
+    return [(bm, bn, bk, w, e, d) for bm in GRID_TILES for bn in GRID_TILES
+            for bk in EXT_BK + GRID_TILES for w in GRID_WAVES for e in EXT_EPT + GRID_EPT
+            for d in GRID_DBUF]
+
+
+def valid_grid(dtype: int, extended: bool = False):
+    """The points of ``raw_grid`` (or ``extended_grid``) that break no rule."""
+    return [p for p in (extended_grid() if extended else raw_grid())
+            if not grid_violations(dtype, *p)]
 
 
 class Operands:

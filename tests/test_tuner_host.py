@@ -7,6 +7,7 @@ import os
 import numpy as np
 import pytest
 
+import paper_1706_10086_amd as mg
 from paper_1706_10086_amd import learn, tune
 
 
@@ -112,3 +113,32 @@ def test_shipped_database_covers_the_registry():
     assert dts == {0, 1}
     n_shapes = len({(r["dtype"], r["m"], r["n"], r["k"]) for r in db.records})
     assert n_shapes == 7000
+
+
+def test_raw_grid_and_validity_rules():
+    g = tune.raw_grid()
+    assert len(g) == 1536 and len(set(g)) == 1536
+    f64, f32 = tune.valid_grid(0), tune.valid_grid(1)
+    # FP32 halves the LDS and accumulator footprint: every valid FP64 point is a
+    # valid FP32 point
+    assert set(f64) < set(f32)
+    # each rule on a point that breaks only it
+    assert tune.grid_violations(0, 256, 256, 64, 4, 4, 1) == ["lds", "acc"]
+    assert tune.grid_violations(1, 256, 256, 64, 4, 4, 1) == ["lds"]
+    assert tune.grid_violations(0, 256, 256, 16, 1, 4, 0) == ["acc"]
+    assert tune.grid_violations(0, 32, 32, 32, 8, 4, 0) == ["mfma", "loads"]
+    assert tune.grid_violations(0, 64, 32, 32, 2, 16, 1) == ["loads"]
+    assert tune.grid_violations(0, 64, 64, 32, 4, 4, 1) == []
+
+
+def test_registry_lies_in_the_valid_space():
+    """Every compiled configuration is a valid point of the extended grid (k-steps
+    of 16 and 2-element runs added); three-stage entries count three stages."""
+    assert len(tune.extended_grid()) == 2560
+    for dt in (mg.F64, mg.F32):
+        ext = set(tune.valid_grid(dt, extended=True))
+        for c in mg.configs(dt):
+            p = (c.bm, c.bn, c.bk, c.waves, c.elems_per_thread, min(c.double_buffer, 1))
+            assert p in ext, c.as_tuple()
+            assert tune.grid_violations(dt, c.bm, c.bn, c.bk, c.waves, c.elems_per_thread,
+                                        c.double_buffer) == [], c.as_tuple()
