@@ -60,7 +60,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extras", action="store_true", help="only the FP64 headline leg")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--leg", choices=["parity", "sweep", "split", "batched", "batched_plan", "tuner"],
+    ap.add_argument("--leg", choices=["parity", "sweep", "split", "batched", "batched_plan", "tuner",
+                                       "memory"],
                     default=None,
                     help="run only this extra leg and print its JSON (for profiling runs)")
     return ap.parse_args()
@@ -310,6 +311,64 @@ def leg_batched(mg, torch, dev, plan_only=False):
     return out
 
 
+def leg_memory(mg, torch, dev, sizes=(1024, 2048, 4096, 8192)):
+    """Operands in device memory against operands in host memory (the paper's
+    unified-against-device-memory comparison, Sec. 3): square FP64 GEMM,
+    alpha = beta = 1, with (a) A, B, C resident in device memory, (b) A, B, C in
+    pinned host memory copied in and C copied back around every call, (c) A, B, C
+    in pinned, mapped host memory read and written in place by the kernel
+    (coherent: uncached; non-coherent: the GPU may cache it)."""
+    log("bench: memory leg, device vs explicit copy vs zero-copy host memory")
+    stream = torch.cuda.current_stream()
+    out = {"inputs": "uniform[-1,1) on the device, alpha = beta = 1, library's default tile choice"}
+    last = {}    # mode -> (n, ms): a host-memory mode is skipped once its time,
+    #              scaled by n^3 from the previous size, would pass 3 s per call
+    for n in sizes:
+        reps = 2 if n >= 8192 else 3
+        g = torch.Generator(device=dev)
+        g.manual_seed(5000 + n)
+        tA, tB, tC = (torch.rand((n, n), device=dev, dtype=torch.float64, generator=g) * 2 - 1
+                      for _ in range(3))
+        hA, hB, hC = (t.cpu().pin_memory() for t in (tA, tB, tC))
+        flops = pm.gemm_flops(n, n, n)
+        row = {}
+        t = timed(lambda: mg.gemm(tA, tB, tC, 1.0, 1.0, stream=stream), stream, reps)
+        row["device_ms"] = round(float(np.mean(t)), 3)
+
+        def explicit():
+            tA.copy_(hA, non_blocking=True)
+            tB.copy_(hB, non_blocking=True)
+            tC.copy_(hC, non_blocking=True)
+            mg.gemm(tA, tB, tC, 1.0, 1.0, stream=stream)
+            hC.copy_(tC, non_blocking=True)
+        t = timed(explicit, stream, reps)
+        row["explicit_copy_ms"] = round(float(np.mean(t)), 3)
+        t = timed(lambda: tA.copy_(hA, non_blocking=True), stream, reps)
+        row["h2d_GBps"] = round(8.0 * n * n / (float(np.mean(t)) * 1e6), 1)
+        for name, coh in (("zero_copy_coherent_ms", True), ("zero_copy_noncoherent_ms", False)):
+            if name in last and last[name][1] * (n / last[name][0]) ** 3 > 3000.0:
+                row[name] = None
+                continue
+            bufs = [mg.HostBuffer(8 * n * n, coh) for _ in range(3)]
+            for b, h in zip(bufs, (hA, hB, hC)):
+                b.array((n, n))[...] = h.numpy()
+            a, b, c = (x.dev for x in bufs)
+            t = timed(lambda: mg._check(mg.gemm_ex_raw(n, n, n, 1.0, a, n, b, n, 1.0, c, n, mg.F64,
+                                                       None, stream.cuda_stream)), stream, reps)
+            row[name] = round(float(np.mean(t)), 3)
+            last[name] = (n, row[name])
+            for x in bufs:
+                x.free()
+        for key in list(row):
+            if key.endswith("_ms") and row[key] is not None:
+                row[key[:-3] + "_tflops"] = round(flops / (row[key] * 1e9), 3)
+        out[str(n)] = row
+        log(f"bench: memory leg N={n}: {row}")
+        del tA, tB, tC, hA, hB, hC
+        torch.cuda.empty_cache()
+    return out
+
+
 def live_recheck(mg, pred, table, count=12):
     """Re-times held-out FP64 shapes now: TFLOP/s of the predicted configuration
     over the best of all registered configurations, measured in this run."""
@@ -387,7 +446,8 @@ def main():
                 "parity": lambda: leg_parity(mg, torch, dev),
                 "batched": lambda: leg_batched(mg, torch, dev),
                 "batched_plan": lambda: leg_batched(mg, torch, dev, plan_only=True),
-                "tuner": lambda: leg_tuner(mg)}
+                "tuner": lambda: leg_tuner(mg),
+                "memory": lambda: leg_memory(mg, torch, dev)}
         print(json.dumps({args.leg: legs[args.leg]()}), flush=True)
         return 0
     log(f"bench: generating N={n} inputs")
@@ -491,6 +551,7 @@ def main():
                          ("sweep", lambda: leg_sweep(mg, torch, dev)),
                          ("split", lambda: leg_split(mg, torch, dev)),
                          ("batched", lambda: leg_batched(mg, torch, dev)),
+                         ("memory", lambda: leg_memory(mg, torch, dev)),
                          ("tuner", lambda: leg_tuner(mg))):
             try:
                 out[name] = fn()

@@ -253,6 +253,27 @@ MGEMM_API int32_t mgemm_config_get(int32_t dtype, int32_t i, mgemm_cfg *out);
  * MGEMM_ERR_HIP (workspace kept) if waiting for that work fails. */
 MGEMM_API int32_t mgemm_release_workspace(void);
 
+/* Host memory that kernels read and write in place (zero copy), for operands
+ * that live in host memory: the counterpart of the paper's comparison of unified
+ * (managed) memory with explicit device memory (Sec. 3, the K80 and P100 runs).
+ * Page-migrating managed memory needs on-demand GPU page faults, which these
+ * GPUs run without; pinned, mapped host memory is the form every kernel can use.
+ *   bytes     size of the allocation (> 0);
+ *   coherent  1: accesses go to host memory uncached (host writes are seen by a
+ *             running kernel); 0: the GPU may cache the memory, and host and
+ *             device see each other's writes only at kernel boundaries and
+ *             stream synchronisation;
+ *   host      receives the host address (for host code);
+ *   dev       receives the device address of the same memory (for A, B, C of
+ *             any call of this library).
+ * The caller owns the memory and frees it with mgemm_host_free(host) once no
+ * queued work uses it.  Returns 0; -1 (bytes <= 0) or -2 (NULL out pointer);
+ * MGEMM_ERR_HIP if the allocation or its mapping fails (nothing is kept). */
+MGEMM_API int32_t mgemm_host_alloc(int64_t bytes, int32_t coherent, void **host, void **dev);
+
+/* Frees memory from mgemm_host_alloc (NULL: no-op); 0 or MGEMM_ERR_HIP. */
+MGEMM_API int32_t mgemm_host_free(void *host);
+
 /* Diagnostic: one matrix-core step on one wave with the fragment layout the
  * tiled kernels assume (lane l supplies A[l%16][l/16] and B[l/16][l%16] and
  * receives column l%16 of D; with q = l/16, accumulator element r holds row

@@ -16,6 +16,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmgemm.so")
@@ -31,7 +32,7 @@ EXPORTED = [
     "gemm", "gemm_ex", "mgemm_set_stream", "mgemm_last_error", "mgemm_config_count",
     "mgemm_config_get", "mgemm_release_workspace", "mgemm_probe_mfma", "mgemm_probe_mfma_raw",
     "gemm_batched", "gemm_batched_plan_create", "gemm_batched_plan_execute",
-    "gemm_batched_plan_destroy", "gemm_batched_plan_info",
+    "gemm_batched_plan_destroy", "gemm_batched_plan_info", "mgemm_host_alloc", "mgemm_host_free",
 ]
 
 
@@ -103,6 +104,10 @@ def lib():
     L.gemm_batched_plan_destroy.restype = i32
     L.gemm_batched_plan_info.argtypes = [p, p, p, p]
     L.gemm_batched_plan_info.restype = i32
+    L.mgemm_host_alloc.argtypes = [i64, i32, ctypes.POINTER(p), ctypes.POINTER(p)]
+    L.mgemm_host_alloc.restype = i32
+    L.mgemm_host_free.argtypes = [p]
+    L.mgemm_host_free.restype = i32
     _lib = L
     return L
 
@@ -133,6 +138,37 @@ def gemm_raw(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, dtype) -> int:
 def gemm_ex_raw(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, dtype, cfg=None, stream=None) -> int:
     return lib().gemm_ex(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, dtype, _cfg_ptr(cfg),
                          stream)
+
+
+class HostBuffer:
+    """Pinned host memory mapped for the GPU (mgemm_host_alloc): ``dev`` is the
+    address kernels use, ``array`` a numpy view of the host side."""
+
+    def __init__(self, nbytes: int, coherent: bool = True):
+        h, d = ctypes.c_void_p(), ctypes.c_void_p()
+        _check(lib().mgemm_host_alloc(int(nbytes), 1 if coherent else 0, ctypes.byref(h),
+                                      ctypes.byref(d)))
+        self.host, self.dev, self.nbytes = h.value, d.value, int(nbytes)
+
+    def array(self, shape, dtype=np.float64, offset: int = 0) -> np.ndarray:
+        """numpy view of ``shape`` elements starting ``offset`` bytes in."""
+        dt = np.dtype(dtype)
+        count = int(np.prod(shape))
+        if offset < 0 or offset + count * dt.itemsize > self.nbytes:
+            raise ValueError("view beyond the buffer")
+        raw = (ctypes.c_char * (count * dt.itemsize)).from_address(self.host + offset)
+        return np.frombuffer(raw, dtype=dt).reshape(shape)
+
+    def free(self) -> None:
+        if self.host:
+            _check(lib().mgemm_host_free(self.host))
+            self.host = self.dev = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
 
 
 def configs(dtype: int) -> list[Cfg]:

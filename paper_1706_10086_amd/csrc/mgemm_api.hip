@@ -320,6 +320,33 @@ int32_t mgemm_config_count(int32_t dtype) {
     return cnt;
 }
 
+int32_t mgemm_host_alloc(int64_t bytes, int32_t coherent, void **host, void **dev) {
+    if (!host || !dev) return set_error(-2, "host or dev is NULL");
+    *host = *dev = nullptr;
+    if (bytes <= 0) return set_error(-1, "bytes <= 0");
+    const unsigned flags =
+        hipHostMallocMapped | (coherent ? hipHostMallocCoherent : hipHostMallocNonCoherent);
+    void *h = nullptr;
+    hipError_t e = hipHostMalloc(&h, (size_t)bytes, flags);
+    if (e != hipSuccess) return hip_error(e, "host_alloc: hipHostMalloc");
+    void *d = nullptr;
+    e = hipHostGetDevicePointer(&d, h, 0);
+    if (e != hipSuccess || !d) {
+        (void)hipHostFree(h);
+        return hip_error(e != hipSuccess ? e : hipErrorInvalidValue,
+                        "host_alloc: hipHostGetDevicePointer");
+    }
+    *host = h;
+    *dev = d;
+    return 0;
+}
+
+int32_t mgemm_host_free(void *host) {
+    if (!host) return 0;
+    hipError_t e = hipHostFree(host);
+    return e == hipSuccess ? 0 : hip_error(e, "host_free: hipHostFree");
+}
+
 int32_t mgemm_config_get(int32_t dtype, int32_t i, mgemm_cfg *out) {
     if (dtype < MGEMM_F64 || dtype > MGEMM_CRT_INT8) return -1;
     int cnt = 0;

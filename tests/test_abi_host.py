@@ -91,3 +91,14 @@ def test_config_registry(L):
     assert L.mgemm_config_count(9) < 0
     c = mg.Cfg()
     assert L.mgemm_config_get(mg.F64, 10 ** 6, ctypes.byref(c)) == -2
+
+
+def test_host_alloc_argument_errors(L):
+    # both are rejected before any HIP call
+    h, d = ctypes.c_void_p(), ctypes.c_void_p()
+    assert L.mgemm_host_alloc(0, 1, ctypes.byref(h), ctypes.byref(d)) == -1
+    assert L.mgemm_host_alloc(-5, 0, ctypes.byref(h), ctypes.byref(d)) == -1
+    assert h.value is None and d.value is None
+    assert L.mgemm_host_alloc(64, 1, None, ctypes.byref(d)) == -2
+    assert L.mgemm_host_alloc(64, 1, ctypes.byref(h), None) == -2
+    assert L.mgemm_host_free(None) == 0
