@@ -255,6 +255,10 @@ def leg_batched(mg, torch, dev, plan_only=False):
     log("bench: FP64 plan timed")
     info = plan.info()
     plan.destroy()
+    tuned = None
+    if not plan_only:
+        tuned = tuned_plan(mg, As, Bs, Cs, mg.F64, stream, flops, PEAK_F64_TFLOPS)
+        log(f"bench: FP64 plan tuned ({tuned['rule']})")
     if plan_only:
         tl = [float("nan")]
     else:
@@ -273,7 +277,8 @@ def leg_batched(mg, torch, dev, plan_only=False):
            "roofline_frac_per_problem": round(bound_s / (gms * 1e-3), 4),
            "per_problem_ms": None if plan_only else round(float(np.mean(tl)), 4),
            "per_problem_tflops": None if plan_only else round(flops / float(np.mean(tl)) / 1e9, 3),
-           "speedup": None if plan_only else round(float(np.mean(tl)) / gms, 3)}
+           "speedup": None if plan_only else round(float(np.mean(tl)) / gms, 3),
+           "tuned": tuned}
     if not plan_only:
         # the oracle on every problem of the batch, all host cores (the first 512
         # problems, scaled by FLOP to the whole batch)
@@ -297,6 +302,10 @@ def leg_batched(mg, torch, dev, plan_only=False):
     tp = timed(plan.execute, stream, 10, warmup=2)
     log("bench: FP32 plan timed")
     plan.destroy()
+    tuned32 = None
+    if not plan_only:
+        tuned32 = tuned_plan(mg, As32, Bs32, Cs32, mg.F32, stream, flops, PEAK_F32_TFLOPS)
+        log(f"bench: FP32 plan tuned ({tuned32['rule']})")
     if plan_only:
         tl = [float("nan")]
     else:
@@ -307,8 +316,23 @@ def leg_batched(mg, torch, dev, plan_only=False):
                   "roofline_frac": round(max(flops / (PEAK_F32_TFLOPS * 1e12), nbytes / 2 / 8e12) /
                                          (g32 * 1e-3), 4),
                   "per_problem_ms": None if plan_only else round(float(np.mean(tl)), 4),
-                  "speedup": None if plan_only else round(float(np.mean(tl)) / g32, 3)}
+                  "speedup": None if plan_only else round(float(np.mean(tl)) / g32, 3),
+                  "tuned": tuned32}
     return out
+
+
+def tuned_plan(mg, As, Bs, Cs, dtype, stream, flops, peak_tflops):
+    """The batch tuner's choice for this batch (every candidate rule's plan timed,
+    5 runs each), re-timed on its own over 10 runs."""
+    from paper_1706_10086_amd import tune
+    cands = tune.tune_batch(As, Bs, Cs, 1.0, 0.0, dtype, reps=5, stream=stream)
+    name, _, _, cfgs = cands[0]
+    t, nb = tune.time_plan(As, Bs, Cs, 1.0, 0.0, dtype, cfgs, reps=10, stream=stream)
+    ms = float(np.mean(t))
+    return {"rule": name, "buckets": nb, "graph_ms": round(ms, 4),
+            "graph_tflops": round(flops / ms / 1e9, 3),
+            "mfma_frac": round(flops / (ms * 1e-3) / (peak_tflops * 1e12), 4),
+            "candidates_ms": {c[0]: round(c[1], 4) for c in cands}}
 
 
 def leg_memory(mg, torch, dev, sizes=(1024, 2048, 4096, 8192)):

@@ -35,6 +35,10 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 typedef float v2f __attribute__((ext_vector_type(2)));
 typedef unsigned u32x4_t __attribute__((ext_vector_type(4)));
 
+// Pointer qualifier for global memory: loads and stores through it compile to
+// global instructions, never to generic (flat) ones.
+#define AS_GLOBAL __attribute__((address_space(1)))
+
 // ---------------------------------------------------------------------------
 // Element-type traits: vector types and the 16x16xK MFMA step.
 // ---------------------------------------------------------------------------
@@ -128,9 +132,12 @@ __device__ __forceinline__ void tile_gemm(const GemmArgs &p, int64_t m0, int64_t
     const int wm = wave / WGN;             // wave position in the work-group grid
     const int wn = wave % WGN;
 
-    const T *__restrict__ A = (const T *)p.A;
-    const T *__restrict__ B = (const T *)p.B;
-    T *__restrict__ C = (T *)p.C;
+    // global address space: the operands of a batched problem come from a
+    // descriptor in memory, and generic (flat) loads would also count against the
+    // LDS wait counter, tying each LDS read to the outstanding prefetch
+    const AS_GLOBAL T *__restrict__ A = (const AS_GLOBAL T *)p.A;
+    const AS_GLOBAL T *__restrict__ B = (const AS_GLOBAL T *)p.B;
+    AS_GLOBAL T *__restrict__ C = (AS_GLOBAL T *)p.C;
     const int64_t lda = p.lda, ldb = p.ldb, ldc = p.ldc;
     const int64_t mrem = p.m - m0;          // valid rows of this tile (may exceed BM)
     const int64_t nrem = p.n - n0;
@@ -160,14 +167,14 @@ __device__ __forceinline__ void tile_gemm(const GemmArgs &p, int64_t m0, int64_t
 #pragma unroll
         for (int r = 0; r < A_RUNS; ++r) {
             const bool rok = a_row[r] < mrem;
-            const T *src = A + (m0 + a_row[r]) * lda + k0 + a_col[r];
+            const AS_GLOBAL T *src = A + (m0 + a_row[r]) * lda + k0 + a_col[r];
 #pragma unroll
             for (int v = 0; v < EPT / 2; ++v) {
                 const int c = a_col[r] + 2 * v;
                 vec2 x = {T(0), T(0)};
                 if (rok) {
                     if (ALIGN && c + 1 < krem) {
-                        x = *(const vec2 *)(src + 2 * v);
+                        x = *(const AS_GLOBAL vec2 *)(src + 2 * v);
                     } else {
                         if (c < krem) x[0] = src[2 * v];
                         if (c + 1 < krem) x[1] = src[2 * v + 1];
@@ -179,14 +186,14 @@ __device__ __forceinline__ void tile_gemm(const GemmArgs &p, int64_t m0, int64_t
 #pragma unroll
         for (int r = 0; r < B_RUNS; ++r) {
             const bool rok = b_row[r] < krem;
-            const T *src = B + (k0 + b_row[r]) * ldb + n0 + b_col[r];
+            const AS_GLOBAL T *src = B + (k0 + b_row[r]) * ldb + n0 + b_col[r];
 #pragma unroll
             for (int v = 0; v < EPT / 2; ++v) {
                 const int c = b_col[r] + 2 * v;
                 vec2 x = {T(0), T(0)};
                 if (rok) {
                     if (ALIGN && c + 1 < nrem) {
-                        x = *(const vec2 *)(src + 2 * v);
+                        x = *(const AS_GLOBAL vec2 *)(src + 2 * v);
                     } else {
                         if (c < nrem) x[0] = src[2 * v];
                         if (c + 1 < nrem) x[1] = src[2 * v + 1];
@@ -286,7 +293,7 @@ __device__ __forceinline__ void tile_gemm(const GemmArgs &p, int64_t m0, int64_t
             for (int j = 0; j < FN; ++j)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    T *c = C + (m0 + wm * WM + i * 16 + E::out_row(kq, r)) * ldc + n0 + wn * WN +
+                    AS_GLOBAL T *c = C + (m0 + wm * WM + i * 16 + E::out_row(kq, r)) * ldc + n0 + wn * WN +
                            j * 16 + l16;
                     *c = read_c ? scale_add(alpha, acc[i][j][r], beta, cv[j][r]) : alpha * acc[i][j][r];
                 }
@@ -303,7 +310,7 @@ __device__ __forceinline__ void tile_gemm(const GemmArgs &p, int64_t m0, int64_t
             for (int r = 0; r < 4; ++r) {
                 const int64_t row = wm * WM + i * 16 + E::out_row(kq, r);
                 if (row >= mrem) continue;
-                T *c = C + (m0 + row) * ldc + n0 + col;
+                AS_GLOBAL T *c = C + (m0 + row) * ldc + n0 + col;
                 *c = read_c ? scale_add(alpha, acc[i][j][r], beta, *c) : alpha * acc[i][j][r];
             }
         }
@@ -393,7 +400,8 @@ splitk_reduce_kernel(const T *__restrict__ W, int S, int64_t m, int64_t n, T alp
 // Waves per SIMD the batched kernel is compiled for: the configuration's
 // occupancy if it names one; for the four-wave 64 x 64 x 16 tile three (it
 // still fits without spilling, and a batch of short tiles is bound by load
-// latency, which more resident work-groups hide).
+// latency, which more resident work-groups hide; FP64 spills at four, FP32 fits
+// four but ran no faster).
 constexpr int batched_waves(int bm, int bn, int bk, int waves, int occ) {
     return occ > 0 ? occ : (bm * bn <= 64 * 64 && bk <= 16 && waves == 4 ? 3 : 1);
 }

@@ -334,6 +334,68 @@ def sweep_set(shapes, dtype, db: DB, reps=2, abandon=2.0, log=print, every=25):
     return new
 
 
+# ---------------------------------------------------------------------------
+# Batched plans: which tile configuration each problem of a batch runs with.
+# The problems of a plan share the GPU, so a choice is judged by timing the
+# whole captured plan, not problem by problem.
+# ---------------------------------------------------------------------------
+def batch_rules(dtype: int) -> dict:
+    """Candidate rules, each mapping a problem (m, n, k) to a configuration tuple:
+    one registered configuration for every problem (three-stage entries are left
+    out: in a plan they run their two-stage fallback, registered on its own), and
+    mixtures of the 64 x 64 four-wave tile with the smallest tile for thin
+    problems (min(m, n) <= T) or a 128 x 128 tile for large ones (min(m, n) >= T)."""
+    cs = [c.as_tuple() for c in configs(dtype) if c.double_buffer < 2]
+    rules = {f"all {c}": (lambda m, n, k, c=c: c) for c in cs}
+    mid = next((c for c in cs if c[:4] == (64, 64, 16, 4)), None)
+    small = min(cs, key=lambda c: (c[0] * c[1], c[2]))
+    big = next((c for c in cs if c[:4] == (128, 128, 16, 4) and c[6] == 0), None)
+    if mid is not None:
+        for T in (32, 48, 64):
+            rules[f"min(m,n) <= {T}: {small}, else {mid}"] = \
+                (lambda m, n, k, T=T: small if min(m, n) <= T else mid)
+        if big is not None:
+            for T in (256, 512):
+                rules[f"min(m,n) >= {T}: {big}, else {mid}"] = \
+                    (lambda m, n, k, T=T: big if min(m, n) >= T else mid)
+    return rules
+
+
+def time_plan(As, Bs, Cs, alphas, betas, dtype, cfgs, reps=5, warmup=2, stream=None):
+    """Device times (ms) of ``reps`` executions of one captured plan, and its
+    bucket count."""
+    import torch
+    from . import BatchedPlan
+    stream = stream or torch.cuda.current_stream()
+    plan = BatchedPlan(As, Bs, Cs, alphas, betas, dtype=dtype, cfgs=cfgs, stream=stream)
+    try:
+        for _ in range(warmup):
+            plan.execute()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+        ev[0].record(stream)
+        for i in range(reps):
+            plan.execute()
+            ev[i + 1].record(stream)
+        ev[-1].synchronize()
+        return [ev[i].elapsed_time(ev[i + 1]) for i in range(reps)], plan.info()["buckets"]
+    finally:
+        plan.destroy()
+
+
+def tune_batch(As, Bs, Cs, alphas=1.0, betas=0.0, dtype=F64, rules=None, reps=5, stream=None):
+    """Times the plan of every candidate rule (``batch_rules``) on this batch;
+    returns [(name, median ms, buckets, per-problem configurations)], fastest first."""
+    rules = rules or batch_rules(dtype)
+    shapes = [(A.shape[0], B.shape[1], A.shape[1]) for A, B in zip(As, Bs)]
+    out = []
+    for name, rule in rules.items():
+        cfgs = [rule(m, n, k) for m, n, k in shapes]
+        t, nb = time_plan(As, Bs, Cs, alphas, betas, dtype, cfgs, reps=reps, stream=stream)
+        out.append((name, float(np.median(t)), nb, cfgs))
+    out.sort(key=lambda r: r[1])
+    return out
+
+
 def main(argv=None):
     import argparse
     ap = argparse.ArgumentParser(description="autotuner sweep (resumable JSONL database)")

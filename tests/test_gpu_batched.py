@@ -211,3 +211,36 @@ def test_plan_without_tile_map(dev, orc):
     plan.destroy()
     del As, Bs, Cs, Cr
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("tdt", [torch.float64, torch.float32])
+def test_batch_tuner_choice(dev, orc, tdt):
+    """The batch tuner times every candidate rule's plan and ranks them; the
+    winning plan (beta = 0, as in the batched workload) gives the same bits as
+    per-problem launches with the configurations it chose."""
+    from paper_1706_10086_amd import tune
+    dt = mg.F32 if tdt == torch.float32 else mg.F64
+    say(f"batch tuner {tdt}")
+    As, Bs, Cs, host = make_batch(dev, 64, 16, 400, 23, tdt)
+    res = tune.tune_batch(As, Bs, Cs, 1.0, 0.0, dt, reps=2)
+    assert len(res) == len(tune.batch_rules(dt))
+    assert [r[1] for r in res] == sorted(r[1] for r in res)
+    name, ms, nb, cfgs = res[0]
+    say(f"  best {name}: {ms:.4f} ms, {nb} bucket(s)")
+    assert nb == len(set(cfgs))
+    plan = mg.BatchedPlan(As, Bs, Cs, 1.0, 0.0, cfgs=cfgs)
+    plan.execute()
+    Cs_ref = [torch.full_like(c, float("nan")) for c in Cs]
+    for A, B, C, c in zip(As, Bs, Cs_ref, cfgs):
+        mg.gemm(A, B, C, 1.0, 0.0, cfg=c)
+    torch.cuda.synchronize()
+    for i, (c, r) in enumerate(zip(Cs, Cs_ref)):
+        assert torch.equal(c, r), i
+    plan.destroy()
+    u = 2.0 ** -53 if tdt == torch.float64 else 2.0 ** -24
+    for i in range(0, len(host), 5):
+        A, B, _ = host[i]
+        ref = orc.gemm_dot2(1.0, A, B)
+        k = A.shape[1]
+        bound = (k + 2) * u / (1 - (k + 2) * u) * (np.abs(A) @ np.abs(B))
+        assert np.all(np.abs(Cs[i].cpu().double().numpy() - ref) <= bound), i
