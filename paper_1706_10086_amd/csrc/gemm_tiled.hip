@@ -98,7 +98,11 @@ struct TileLds {
 // and sBbase are the work-group's LDS stages (TileLds sizes); the function ends
 // with a barrier after the last read of LDS, so a caller may reuse the stages
 // for another tile right away.
-template <typename T, int BM, int BN, int BK, int WGM, int WGN, int EPT, int DBUF, bool ALIGN>
+// SKIP_DEAD: on edge tiles a wave whose part of the tile lies wholly outside C
+// runs no matrix-core steps (it still loads and stores its share of the LDS
+// tiles; its results are never stored, and every stored sum is unchanged).
+template <typename T, int BM, int BN, int BK, int WGM, int WGN, int EPT, int DBUF, bool ALIGN,
+          bool SKIP_DEAD = false>
 __device__ __forceinline__ void tile_gemm(const GemmArgs &p, int64_t m0, int64_t n0, T *sAbase,
                                           T *sBbase) {
     typedef Elem<T> E;
@@ -253,6 +257,13 @@ __device__ __forceinline__ void tile_gemm(const GemmArgs &p, int64_t m0, int64_t
         }
     };
 
+    // whether any row and column of this wave's part of the tile lie inside C
+    // (uniform per wave)
+    bool live = true;
+    if (SKIP_DEAD)
+        live = mrem > (int64_t)__builtin_amdgcn_readfirstlane(wm) * WM &&
+               nrem > (int64_t)__builtin_amdgcn_readfirstlane(wn) * WN;
+
     const int64_t nk = (p.k + BK - 1) / BK;
     load_tiles(0);
     store_tiles(0);
@@ -261,7 +272,7 @@ __device__ __forceinline__ void tile_gemm(const GemmArgs &p, int64_t m0, int64_t
         const int cur = DBUF ? (int)(kt & 1) : 0;
         const bool more = kt + 1 < nk;
         if (more) load_tiles((kt + 1) * BK);
-        multiply(cur);
+        if (live) multiply(cur);
         if (more) {
             if (!DBUF) __syncthreads();
             store_tiles(DBUF ? cur ^ 1 : 0);
@@ -486,9 +497,10 @@ gemm_batched_kernel(const BatchProblem *__restrict__ probs, const uint64_t *__re
         }
         // the tile runs gemm_ex's code for its problem's row alignment
         if (bp.aligned)
-            tile_gemm<T, BM, BN, BK, WGM, WGN, EPT, DBUF, true>(bp.g, tm * BM, tn * BN, sA, sB);
+            tile_gemm<T, BM, BN, BK, WGM, WGN, EPT, DBUF, true, true>(bp.g, tm * BM, tn * BN, sA, sB);
         else
-            tile_gemm<T, BM, BN, BK, WGM, WGN, EPT, DBUF, false>(bp.g, tm * BM, tn * BN, sA, sB);
+            tile_gemm<T, BM, BN, BK, WGM, WGN, EPT, DBUF, false, true>(bp.g, tm * BM, tn * BN, sA,
+                                                                        sB);
         __syncthreads();                  // every wave has read the current index
         if (threadIdx.x == 0) next = settle();
         __syncthreads();
