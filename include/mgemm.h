@@ -104,11 +104,12 @@ MGEMM_API int32_t gemm(int64_t m, int64_t n, int64_t k, double alpha,
  * that is not in the registry for dtype gives -13) and stream (argument 14,
  * a hipStream_t; NULL: the current library stream).
  *
- * Split-k (MGEMM_F64, cfg == NULL only): when the chosen tile leaves fewer than
- * about four work-groups per compute unit and k >= 512, k is cut into S <= 16
- * ranges (multiples of 256; computed with the three-stage 128 x 128 tile where its
- * requirements hold and it fills the GPU); their partial products go to the library-owned
- * device workspace (S*m*n*8 bytes, grown on demand, MGEMM_ERR_NOMEM if it
+ * Split-k (MGEMM_F64 and MGEMM_F32, cfg == NULL only): when the chosen tile
+ * leaves fewer than about four work-groups per compute unit and k >= 512, k is
+ * cut into S <= 16 ranges (multiples of 256; computed with the three-stage
+ * 128 x 128 tile where its requirements hold and it fills the GPU, else, for
+ * MGEMM_F64 only, with the chosen tile); their partial products go to the library-owned
+ * device workspace (S*m*n*8 bytes, S*m*n*4 for FP32, grown on demand, MGEMM_ERR_NOMEM if it
  * cannot be, kept until mgemm_release_workspace(); calls on one device that use
  * it are ordered through it) and one kernel adds them in range order and applies
  * alpha and beta.  Results are deterministic; they can differ in the last bits
@@ -249,7 +250,7 @@ MGEMM_API int32_t mgemm_config_count(int32_t dtype);
 MGEMM_API int32_t mgemm_config_get(int32_t dtype, int32_t i, mgemm_cfg *out);
 
 /* Frees the library-owned workspace of the current device (split dtypes and
- * FP64 split-k) once the work that last used it has finished; 0 on success,
+ * split-k) once the work that last used it has finished; 0 on success,
  * MGEMM_ERR_HIP (workspace kept) if waiting for that work fails. */
 MGEMM_API int32_t mgemm_release_workspace(void);
 

@@ -824,23 +824,30 @@ hipError_t launch_splitk(const GemmArgs &a, int S, int64_t kc, void *W, hipStrea
     return hipGetLastError();
 }
 
-// FP64 split-k with the three-stage 128 x 128 x 16 eight-wave tile: its
-// requirements are those of launch_pipe (16-byte rows and bases, 32-bit panel
-// offsets); false if they do not hold.
-bool pipe_splitk_f64_eligible(const GemmArgs &a) {
-    constexpr int64_t EPU = 2, BM = 128, BK = 16, BN = 128;
+// Split-k with the three-stage 128 x 128 eight-wave tile (k-step 16 for FP64, 32
+// for FP32): its requirements are those of launch_pipe (16-byte rows and bases,
+// 32-bit panel offsets); false if they do not hold.
+bool pipe_splitk_eligible(const GemmArgs &a, int32_t dtype) {
+    const int64_t es = dtype == MGEMM_F32 ? 4 : 8;
+    const int64_t EPU = 16 / es, BM = 128, BN = 128, BK = dtype == MGEMM_F32 ? 32 : 16;
     return a.k >= 1 && a.n >= EPU && a.n % EPU == 0 && a.lda % EPU == 0 && a.ldb % EPU == 0 &&
            ((uintptr_t)a.A % 16) == 0 && ((uintptr_t)a.B % 16) == 0 &&
-           BM * a.lda * 8 < ((int64_t)1 << 31) && (BK * a.ldb + BN) * 8 < ((int64_t)1 << 31);
+           BM * a.lda * es < ((int64_t)1 << 31) && (BK * a.ldb + BN) * es < ((int64_t)1 << 31);
 }
 
-hipError_t launch_pipe_splitk_f64(const GemmArgs &a, int S, int64_t kc, void *W, hipStream_t s) {
-    if (!pipe_splitk_f64_eligible(a)) return hipErrorInvalidValue;
+hipError_t launch_pipe_splitk(const GemmArgs &a, int32_t dtype, int S, int64_t kc, void *W,
+                              hipStream_t s) {
+    if (!pipe_splitk_eligible(a, dtype)) return hipErrorInvalidValue;
     const int64_t blocks = ((a.m + 127) / 128) * ((a.n + 127) / 128);
     if (blocks <= 0) return hipSuccess;
     if (blocks > 0x7fffffff || S < 1 || S > 65535) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((gemm_pipe_splitk_kernel<double, 128, 128, 16, 4, 2>),
-                       dim3((unsigned)blocks, (unsigned)S), dim3(512), 0, s, a, kc, (double *)W);
+    if (dtype == MGEMM_F32)
+        hipLaunchKernelGGL((gemm_pipe_splitk_kernel<float, 128, 128, 32, 4, 2>),
+                           dim3((unsigned)blocks, (unsigned)S), dim3(512), 0, s, a, kc, (float *)W);
+    else
+        hipLaunchKernelGGL((gemm_pipe_splitk_kernel<double, 128, 128, 16, 4, 2>),
+                           dim3((unsigned)blocks, (unsigned)S), dim3(512), 0, s, a, kc,
+                           (double *)W);
     return hipGetLastError();
 }
 

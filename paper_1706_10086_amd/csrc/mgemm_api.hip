@@ -194,15 +194,16 @@ const KernelEntry *choose_entry(int32_t dtype, int64_t m, int64_t n, const mgemm
 
 int32_t split_gemm(const GemmArgs &a, int32_t dtype, hipStream_t s);
 
-// Split-k for the built-in FP64 choice: when the chosen tile leaves fewer than
-// about four work-groups per compute unit, k is cut into S ranges of kc values (a
-// multiple of SPLITK_MIN_K, itself a multiple of every tile's BK; the last range
-// is the short one); the S partial products go to the library workspace and one
-// reduction kernel adds them in order and applies alpha and beta.  The ranges run
-// on the three-stage 128 x 128 tile (one work-group per compute unit) when that
-// fills at least three quarters of the compute units in one round, else on the
-// chosen two-stage tile (64 x 64 or 32 x 32) with about four work-groups per
-// compute unit.
+// Split-k for the built-in choice: when that fell back to a 64 x 64 or 32 x 32
+// tile and still leaves fewer than about four work-groups per compute unit, k is
+// cut into S ranges of kc values (a multiple of SPLITK_MIN_K, itself a multiple of
+// every tile's BK; the last range is the short one); the S partial products go to
+// the library workspace and one reduction kernel adds them in order and applies
+// alpha and beta.  The ranges run on the three-stage 128 x 128 tile (one
+// work-group per compute unit; FP64 and FP32) when that fills at least three
+// quarters of the compute units in one round, else, for FP64 only, on the chosen
+// two-stage tile with about four work-groups per compute unit (for FP32, twice as
+// fast per tile, that lost 4 % to the extra reduction, so FP32 then runs whole).
 constexpr int64_t SPLITK_MIN_K = 256;
 constexpr int SPLITK_MAX = 16;
 
@@ -236,13 +237,14 @@ static void cut_k(int64_t k, int64_t want, SplitPlan &sp) {
     sp.kc = kc;
 }
 
-static SplitPlan splitk_plan(const GemmArgs &a, const KernelEntry *e) {
+static SplitPlan splitk_plan(const GemmArgs &a, const KernelEntry *e, int32_t dtype) {
     SplitPlan sp;
     const int cus = compute_units();
     const int64_t tiles = tiles_of(a.m, a.n, e->cfg);
-    if (cus <= 0 || tiles <= 0 || !e->splitk[0]) return sp;
+    // only when the built-in choice fell back to a small tile for want of tiles
+    if (cus <= 0 || tiles <= 0 || e->cfg.bm * e->cfg.bn > 64 * 64) return sp;
     if ((4 * (int64_t)cus + tiles - 1) / tiles < 2) return sp;       // enough tiles already
-    if (pipe_splitk_f64_eligible(a)) {
+    if (pipe_splitk_eligible(a, dtype)) {
         const int64_t t128 = ((a.m + 127) / 128) * ((a.n + 127) / 128);
         SplitPlan pp;
         cut_k(a.k, cus / t128, pp);
@@ -251,6 +253,7 @@ static SplitPlan splitk_plan(const GemmArgs &a, const KernelEntry *e) {
             return pp;
         }
     }
+    if (!e->splitk[0]) return sp;          // no two-stage split-k for this entry (FP32)
     cut_k(a.k, (4 * (int64_t)cus + tiles - 1) / tiles, sp);
     return sp;
 }
@@ -259,7 +262,7 @@ static int32_t run_splitk(const KernelEntry *e, const GemmArgs &a, int32_t dtype
                           const SplitPlan &sp, hipStream_t s) {
     const size_t es = dtype == MGEMM_F32 ? 4 : 8;
     return with_workspace((size_t)sp.S * a.m * a.n * es, s, [&](uint8_t *W) -> int32_t {
-        hipError_t he = sp.pipe ? launch_pipe_splitk_f64(a, sp.S, sp.kc, W, s)
+        hipError_t he = sp.pipe ? launch_pipe_splitk(a, dtype, sp.S, sp.kc, W, s)
                                 : e->splitk[al ? 0 : 1](a, sp.S, sp.kc, W, s);
         if (he == hipSuccess) he = splitk_reduce(dtype, W, sp.S, a, s);
         return he == hipSuccess ? 0 : hip_error(he, "split-k launch");
@@ -292,8 +295,8 @@ int32_t gemm_ex(int64_t m, int64_t n, int64_t k, double alpha, const void *A, in
     const KernelEntry *e = choose_entry(dtype, m, n, cfg, &err);
     if (!e) return err;
     const bool al = rows_aligned(A, lda, B, ldb, dtype);
-    if (!cfg && e->splitk[0]) {
-        const SplitPlan sp = splitk_plan(a, e);
+    if (!cfg) {
+        const SplitPlan sp = splitk_plan(a, e, dtype);
         if (sp.S > 1) return run_splitk(e, a, dtype, al, sp, s);
     }
     hipError_t he = (al ? e->launch : e->launch_unaligned)(a, s);

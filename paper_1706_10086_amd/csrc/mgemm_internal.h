@@ -108,10 +108,12 @@ int crt_operand_bits(int64_t k);
 hipError_t crt_launch(const GemmArgs &g, hipStream_t s, const int *e, const int *fexp, int bits,
                       int8_t *QA, int8_t *QB, uint8_t *R, int64_t mp, int64_t np, int64_t kp);
 
-// FP64 split-k partials with the three-stage 128 x 128 x 16 tile (same contract
-// as SplitkLaunchFn); hipErrorInvalidValue unless pipe_splitk_f64_eligible.
-bool pipe_splitk_f64_eligible(const GemmArgs &a);
-hipError_t launch_pipe_splitk_f64(const GemmArgs &a, int S, int64_t kc, void *W, hipStream_t s);
+// Split-k partials with the three-stage 128 x 128 tile, FP64 or FP32 (dtype;
+// otherwise the contract of SplitkLaunchFn); hipErrorInvalidValue unless
+// pipe_splitk_eligible.
+bool pipe_splitk_eligible(const GemmArgs &a, int32_t dtype);
+hipError_t launch_pipe_splitk(const GemmArgs &a, int32_t dtype, int S, int64_t kc, void *W,
+                              hipStream_t s);
 
 // C = alpha * (sum of the S partial planes of W, in plane order) + beta * C.
 hipError_t splitk_reduce(int32_t dtype, const void *W, int S, const GemmArgs &a, hipStream_t s);

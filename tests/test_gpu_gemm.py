@@ -182,12 +182,13 @@ SPLITK_SHAPES = [(1024, 1024, 1024), (896, 1024, 1536), (1024, 512, 4096), (1024
                  (300, 200, 600), (511, 130, 513)]
 
 
-@pytest.mark.parametrize("dtype", [mg.F64])
+@pytest.mark.parametrize("dtype", [mg.F64, mg.F32])
 def test_split_k_default_choice(dev, orc, dtype):
-    """FP64 outputs whose chosen tile leaves fewer than about four work-groups per
+    """Outputs whose chosen tile leaves fewer than about four work-groups per
     compute unit, with k >= 512, run split-k under the built-in choice (k cut into
-    ranges of 256j, partial products reduced in order): every element within
-    gamma_{k+2} of the double-double oracle, normwise <= 1e-13, run-to-run
+    ranges of 256j, partial products reduced in order; FP32 only on the
+    three-stage tile, whose rows must be 16-byte aligned): every element within
+    gamma_{k+2} of the double-double oracle, FP64 normwise <= 1e-13, run-to-run
     identical, C not read when beta = 0."""
     u = 2.0 ** -24 if dtype == mg.F32 else 2.0 ** -53
     for (m, n, k) in SPLITK_SHAPES:
@@ -213,11 +214,15 @@ def test_split_k_default_choice(dev, orc, dtype):
     n = 1024
     A = synth.uniform_pm1((n, n), 31)
     B = synth.uniform_pm1((n, n), 32)
+    if dtype == mg.F32:
+        A, B = (x.astype(np.float32).astype(np.float64) for x in (A, B))
     whole_cfg = [c for c in mg.configs(dtype) if (c.bm, c.bn, c.bk, c.waves) == (64, 64, 16, 4)][0]
     split = run_gemm(dev, A, B, np.zeros((n, n)), 1.0, 0.0, dtype=dtype)
     whole = run_gemm(dev, A, B, np.zeros((n, n)), 1.0, 0.0, dtype=dtype, cfg=whole_cfg)
     assert not np.array_equal(split, whole)
     assert np.linalg.norm(split - whole) <= 4 * n * u * np.linalg.norm(whole)
+    if dtype == mg.F32:
+        return
     # the same k ranges on the two-stage tile (an odd leading dimension of A rules
     # out the three-stage kernel): every tile sums a range in the same order, so
     # both splits agree bit for bit
