@@ -13,7 +13,8 @@
  * Layout   Row-major.  A is m x k with lda >= max(1,k); B is k x n with
  *          ldb >= max(1,n); C is m x n with ldc >= max(1,n).  Leading dimensions
  *          count elements.  There are no transpose flags (the paper has none).
- * Pointers A, B, C are DEVICE pointers on the current HIP device.  The caller owns
+ * Pointers A, B, C are DEVICE pointers on the current HIP device (device memory,
+ *          or the device address of mapped host memory, mgemm_host_alloc).  The caller owns
  *          them; the library never frees, reallocates or keeps them after the call
  *          (batched plans keep them until destroyed, see below).  C must not
  *          overlap A or B.
@@ -163,9 +164,9 @@ MGEMM_API int32_t gemm_batched(int64_t count, const int64_t *m, const int64_t *n
 
 /* Builds a reusable plan for one batched launch: problems are grouped by tile
  * configuration (cfgs[i]; when cfgs is NULL every problem uses the registered
- * 64x64x16 four-wave configuration) and row alignment; per group one persistent
- * kernel takes C tiles from an atomic work list; all groups are captured into one
- * HIP graph.  The plan keeps the problem
+ * 64x64x16 four-wave configuration); per group one persistent kernel takes C
+ * tiles from per-XCD atomic work lists, each tile running the code path of its
+ * problem's row alignment; all groups are captured into one HIP graph.  The plan keeps the problem
  * descriptors (pointers, sizes, alpha, beta) -- the matrices must stay valid and
  * are read at each execution.  Problems with k == 0 or alpha == 0 are rejected
  * (MGEMM_ERR_PLAN).  stream: the stream executions run on (NULL: null stream).
