@@ -315,12 +315,13 @@ def test_three_stage_matches_two_stage_bitwise(dev, orc, padded, dtype):
             assert err <= (1e-13 if dtype == mg.F64 else 1e-5), (cfg, m, n, k, err)
 
 
-@pytest.mark.parametrize("n", [8192])
+@pytest.mark.parametrize("n", [8192, 16384])
 def test_full_size_sampled_rows(dev, orc, n):
-    """The square benchmark size with the default configuration: 64 sampled rows
-    recomputed by the oracle; normwise error over the sample <= 1e-13."""
+    """The square benchmark size and the sweep's largest with the default
+    configuration: 64 sampled rows recomputed by the oracle; normwise error over the
+    sample <= 1e-13."""
     say(f"full size n={n}: generating inputs")
-    sa, sb, sc = synth.seeds_for(1, 13)
+    sa, sb, sc = synth.seeds_for(1, int(np.log2(n)))
     A = synth.uniform_pm1((n, n), sa)
     B = synth.uniform_pm1((n, n), sb)
     C = synth.uniform_pm1((n, n), sc)
@@ -336,3 +337,24 @@ def test_full_size_sampled_rows(dev, orc, n):
     err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
     say(f"  sampled normwise err {err:.3e}")
     assert err <= 1e-13
+
+
+def test_full_size_fp32_sampled_rows(dev, orc):
+    """FP32 at the square benchmark size, default configuration: 64 sampled rows
+    against the FP64 oracle on the same float inputs, every element within
+    gamma_{k+2} with u = 2^-24."""
+    n = 8192
+    say(f"full size fp32 n={n}: generating inputs")
+    sa, sb, sc = synth.seeds_for(1, 13)
+    A, B, C = (synth.uniform_pm1((n, n), s).astype(np.float32) for s in (sa, sb, sc))
+    tA, tB, tC = (torch.from_numpy(X).to(dev) for X in (A, B, C))
+    say("  gemm")
+    mg.gemm(tA, tB, tC, 1.0, 1.0)
+    torch.cuda.synchronize()
+    rows = np.unique(np.concatenate([synth.log_uniform_int(64, 6, 1, n) - 1, [0, n - 1]]))
+    got = tC[torch.from_numpy(rows).to(dev)].cpu().double().numpy()
+    A64, B64, C64 = A[rows].astype(np.float64), B.astype(np.float64), C[rows].astype(np.float64)
+    say(f"  oracle on {len(rows)} rows")
+    ref = orc.gemm_dot2(1.0, A64, B64, 1.0, C64, nthreads=orc.num_procs())
+    bound = gamma(n + 2, 2.0 ** -24) * (np.abs(A64) @ np.abs(B64) + np.abs(C64))
+    assert np.all(np.abs(got - ref) <= bound)

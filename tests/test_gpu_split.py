@@ -172,18 +172,18 @@ def test_deterministic_and_workspace_release(dev, dtype):
     assert torch.equal(C1, C2)
 
 
+@pytest.mark.parametrize("n", [4096, 8192])
 @pytest.mark.parametrize("dtype", DTYPES)
-def test_full_size_4096_sampled_rows(dev, orc, dtype):
-    """The split-precision workload size N = 4096 (wide-range inputs): 8 sampled
-    rows recomputed by the oracle's split model, bitwise."""
+def test_full_size_sampled_rows(dev, orc, dtype, n):
+    """The split-precision workload sizes N = 4096 and 8192 (wide-range inputs):
+    6 sampled rows recomputed by the oracle's split model, bitwise."""
     fmt, S = FMT[dtype]
-    n = 4096
     say(f"split {mg.DTYPE_NAMES[dtype]} n={n}: inputs")
-    sa, sb, _ = synth.seeds_for(2, 12)
+    sa, sb, _ = synth.seeds_for(2, int(np.log2(n)))
     A = synth.wide_range((n, n), sa)
     B = synth.wide_range((n, n), sb)
     got = gpu_split(dev, A, B, np.zeros((n, n)), 1.0, 0.0, dtype)
-    rows = np.array([0, 1, 777, 2048, 3001, 4095])
+    rows = np.array([0, 1, 777, n // 2, n - 1095, n - 1])
     say(f"  oracle split model on {len(rows)} rows")
     want = orc.split_gemm(1.0, A[rows], B, fmt=fmt, S=S, nthreads=orc.num_procs())
     assert np.array_equal(got[rows], want)
