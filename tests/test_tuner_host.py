@@ -142,3 +142,23 @@ def test_registry_lies_in_the_valid_space():
             assert p in ext, c.as_tuple()
             assert tune.grid_violations(dt, c.bm, c.bn, c.bk, c.waves, c.elems_per_thread,
                                         c.double_buffer) == [], c.as_tuple()
+
+
+def test_batch_rules_map_every_shape_to_a_registered_configuration():
+    shapes = [(16, 16, 16), (31, 1000, 17), (48, 48, 900), (300, 700, 64), (1024, 1024, 1024),
+              (600, 20, 512)]
+    for dt in (mg.F64, mg.F32):
+        reg = {c.as_tuple() for c in mg.configs(dt)}
+        rules = tune.batch_rules(dt)
+        # one rule per registered two-stage configuration, plus the mixtures
+        singles = [r for r in rules if r.startswith("all ")]
+        assert len(singles) == sum(1 for c in mg.configs(dt) if c.double_buffer < 2)
+        assert len(rules) > len(singles)
+        for name, rule in rules.items():
+            got = {rule(m, n, k) for m, n, k in shapes}
+            assert got <= reg, name
+            assert all(c[5] < 2 for c in got), name        # never a three-stage entry
+            assert len(got) <= 2, name
+        # a mixture gives thin problems the smallest tile and the rest the 64x64 one
+        mix = next(r for n_, r in rules.items() if n_.startswith("min(m,n) <= 32"))
+        assert mix(31, 1000, 17)[:2] == (32, 32) and mix(300, 700, 64)[:2] == (64, 64)
