@@ -247,3 +247,34 @@ def test_split_bf16_meets_1e14_on_wide_range_inputs(orc):
     plain = orc.gemm_f64(1.0, A, B, nthreads=8)
     err_plain = np.linalg.norm(plain - ref) / np.linalg.norm(ref)
     assert err_plain <= 1e-14
+
+
+def test_fp8_slices_are_nearest_integers(orc):
+    """e4m3 slices (b1 = 4, then b = 5 bits) round to nearest, ties to even: the
+    first slice of 0.75*2^e is 12; 0.5 + 2^-5 scales to 8.5 -> 8 with remainder +0.5,
+    whose second slice is 0.5 * 2^5 = 16; 0.5 + 3*2^-5 scales to 9.5 -> 10 with
+    remainder -0.5 -> -16; every slice stays within |q| <= 16."""
+    A = np.array([[0.75, 0.5 + 2.0 ** -5, 0.5 + 3 * 2.0 ** -5, -0.5 - 2.0 ** -5]])
+    e = orc.split_row_exponents(A)
+    assert e[0] == 0
+    Q, rem = orc.split_slices_rows(A, e, orc.FMT_E4M3, 3)
+    assert list(Q[:, 0, 0]) == [12, 0, 0]
+    assert list(Q[:, 0, 1]) == [8, 16, 0]
+    assert list(Q[:, 0, 2]) == [10, -16, 0]
+    assert list(Q[:, 0, 3]) == [-8, -16, 0]
+    assert np.all(rem[0] == 0.0)
+    assert np.all(np.abs(Q.astype(np.int64)) <= 16)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("fmt,S", [(1, 11), (2, 8)])
+def test_split_fp8_and_int8_meet_1e14_on_wide_range_inputs(orc, fmt, S):
+    """The FP8 e4m3 and int8 slice models on the stress distribution: within 1e-14
+    of the double-double oracle, like the bfloat16 model."""
+    n = 256
+    A = synth.wide_range((n, n), 2001)
+    B = synth.wide_range((n, n), 2002)
+    ref = orc.gemm_dot2(1.0, A, B, nthreads=8)
+    got = orc.split_gemm(1.0, A, B, fmt=fmt, S=S, nthreads=8)
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    assert err <= 1e-14, err
