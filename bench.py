@@ -394,23 +394,26 @@ def leg_memory(mg, torch, dev, sizes=(1024, 2048, 4096, 8192)):
 
 
 def live_recheck(mg, pred, table, count=12):
-    """Re-times held-out FP64 shapes now: TFLOP/s of the predicted configuration
-    over the best of all registered configurations, measured in this run."""
+    """Re-times held-out FP64 shapes now: TFLOP/s of the predicted configuration,
+    and of the library's built-in choice (no configuration named), over the best of
+    all registered configurations, measured in this run."""
     import torch
     from paper_1706_10086_amd import learn, tune
     shapes = [s for s in tune.shape_set("heldout") if 2.0 * s[0] * s[1] * s[2] < 2e11][:count]
     choice = learn.predict(pred, [(mg.F64, *s) for s in shapes])
-    fr = []
+    fr, fb = [], []
     for (m, n, k), c in zip(shapes, choice):
         ops = tune.Operands(m, n, k, mg.F64)
         tf = {}
         for cfg in mg.configs(mg.F64):
             t = tune.time_config(ops, mg.F64, cfg, warmup=1, reps=3)
             tf[cfg.as_tuple()] = tune.flops(m, n, k) / (min(t) * 1e9)
+        t = tune.time_config(ops, mg.F64, None, warmup=1, reps=3)
         fr.append(tf[table[c][1]] / max(tf.values()))
+        fb.append(tune.flops(m, n, k) / (min(t) * 1e9) / max(tf.values()))
         del ops
     torch.cuda.empty_cache()
-    return learn.summarize(np.array(fr))
+    return learn.summarize(np.array(fr)), learn.summarize(np.array(fb))
 
 
 def leg_tuner(mg):
@@ -436,7 +439,7 @@ def leg_tuner(mg):
     single = learn.summarize(learn.achieved(dho, [base[s[0]] for s in dho.shapes]))
     top3 = learn.summarize(learn.top_k_fallback(dho, pred, 3))
     log("bench: tuner leg, live re-timing of held-out shapes")
-    live = live_recheck(mg, pred, table)
+    live, builtin = live_recheck(mg, pred, table)
     return {"database": "paper_1706_10086_amd/data/tune_db.json.gz (MI355X sweep: 3000 train + "
                         "500 held-out shapes, m,n,k log-uniform in [64,16384], FP64 and FP32, "
                         "every registered configuration)",
@@ -444,7 +447,7 @@ def leg_tuner(mg):
             "train_s": round(t_train, 2), "mlp": mlp, "single_best_config": single,
             "mlp_top3_measured": top3, "regret_geomean": round(1.0 - mlp["geomean"], 4),
             "gain_over_single": round(mlp["geomean"] / single["geomean"], 4),
-            "live_recheck_f64": live}
+            "live_recheck_f64": live, "builtin_choice_live_f64": builtin}
 
 
 def main():

@@ -105,6 +105,13 @@ MGEMM_API int32_t gemm(int64_t m, int64_t n, int64_t k, double alpha,
  * that is not in the registry for dtype gives -13) and stream (argument 14,
  * a hipStream_t; NULL: the current library stream).
  *
+ * The library's choice (MGEMM_F64, MGEMM_F32): the largest preferred tile that
+ * still gives enough work-groups for the m x n output; split-k below; and, for rows
+ * the three-stage kernels cannot load (n, lda, ldb not multiples of 16 bytes, or A,
+ * B not 16-byte aligned) with m, n, k in [64, 16384], the configuration measured
+ * fastest on the tuner's shapes of the same (floor(log2 m), floor(log2 n),
+ * floor(log2 k)) cell.
+ *
  * Split-k (MGEMM_F64 and MGEMM_F32, cfg == NULL only): when the chosen tile
  * leaves fewer than about four work-groups per compute unit and k >= 512, k is
  * cut into S <= 16 ranges (multiples of 256; computed with the three-stage

@@ -12,6 +12,7 @@
 
 #include <algorithm>
 
+#include "choice_table.h"
 #include "mgemm_internal.h"
 
 namespace mgemm {
@@ -161,6 +162,36 @@ static const KernelEntry *find_entry(const KernelEntry *reg, int cnt, const mgem
     return nullptr;
 }
 
+// The configuration measured fastest for an m x n x k product whose rows the
+// three-stage kernels cannot load (choice_table.h: the tuner database's shapes of
+// the same log2 cell); NULL outside the table's range or for an unlisted cell.
+static const KernelEntry *measured_entry(int32_t dtype, int64_t m, int64_t n, int64_t k) {
+    constexpr int64_t lo = (int64_t)1 << CHOICE_LOG2_LO, hi = (int64_t)1 << CHOICE_LOG2_HI;
+    if (m < lo || n < lo || k < lo || m > hi || n > hi || k > hi) return nullptr;
+    auto lg = [](int64_t x) { int l = 0; while (x >> (l + 1)) ++l; return l; };
+    const ChoiceCell key = {(int8_t)dtype, (int8_t)lg(m), (int8_t)lg(n), (int8_t)lg(k)};
+    auto less = [](const ChoiceCell &a, const ChoiceCell &b) {
+        if (a.dtype != b.dtype) return a.dtype < b.dtype;
+        if (a.lm != b.lm) return a.lm < b.lm;
+        if (a.ln != b.ln) return a.ln < b.ln;
+        return a.lk < b.lk;
+    };
+    const ChoiceCell *end = kChoiceCells + CHOICE_CELLS;
+    const ChoiceCell *c = std::lower_bound(kChoiceCells, end, key, less);
+    if (c == end || less(key, *c)) return nullptr;
+    int cnt = 0;
+    const KernelEntry *reg = registry(dtype, &cnt);
+    const mgemm_cfg cfg = {c->bm, c->bn, c->bk, c->waves, c->ept, c->dbuf, c->occ};
+    return find_entry(reg, cnt, cfg);
+}
+
+// Whether the three-stage kernels can load these rows (16-byte rows and bases).
+static bool rows_whole_loads(const GemmArgs &a, int32_t dtype) {
+    const int64_t epu = dtype == MGEMM_F32 ? 4 : 2;
+    return a.n % epu == 0 && a.lda % epu == 0 && a.ldb % epu == 0 &&
+           ((uintptr_t)a.A % 16) == 0 && ((uintptr_t)a.B % 16) == 0;
+}
+
 static bool aligned_rows(const void *p, int64_t ld, size_t es) {
     return ((uintptr_t)p % (2 * es)) == 0 && (ld % 2) == 0;
 }
@@ -298,6 +329,12 @@ int32_t gemm_ex(int64_t m, int64_t n, int64_t k, double alpha, const void *A, in
     if (!cfg) {
         const SplitPlan sp = splitk_plan(a, e, dtype);
         if (sp.S > 1) return run_splitk(e, a, dtype, al, sp, s);
+        // rows the three-stage kernels cannot load: the configuration measured
+        // fastest for shapes like this one (the preference list favours them)
+        if (!rows_whole_loads(a, dtype)) {
+            const KernelEntry *t = measured_entry(dtype, m, n, k);
+            if (t) e = t;
+        }
     }
     hipError_t he = (al ? e->launch : e->launch_unaligned)(a, s);
     if (he != hipSuccess) return hip_error(he, "gemm launch");

@@ -86,3 +86,46 @@ def test_chooser_database_then_model():
         ref = A @ B
         err = float(torch.linalg.norm(C.cpu() - ref) / torch.linalg.norm(ref))
         assert err <= 1e-13
+
+
+def test_builtin_choice_for_rows_the_three_stage_kernels_cannot_load():
+    """gemm without a configuration, on held-out shapes whose n or k rules out the
+    three-stage kernels (and whose output is large enough that split-k does not
+    apply): it runs the configuration of the shape's cell in the library's measured
+    table, bit for bit the same as naming that configuration, and within the FP64 /
+    FP32 tolerances of the oracle on sampled rows."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import oracle
+    import synth
+    from paper_1706_10086_amd.csrc import gen_choice_table as gen
+    db = tune.load_compact(DB_PATH)
+    table = gen.build_table(db.records, set(tune.shape_set("train")))
+    dev = torch.device("cuda:0")
+    for dt in (mg.F64, mg.F32):
+        shapes = [s for s in tune.shape_set("heldout")
+                  if gen.three_stage_ineligible(dt, s[1], s[2]) and 2.0 * s[0] * s[1] * s[2] < 4e10
+                  and (-(-s[0] // 128)) * (-(-s[1] // 64)) >= 256
+                  and gen.cell_of(*s) in table[dt]][:6]
+        assert len(shapes) == 6
+        tdt = torch.float32 if dt == mg.F32 else torch.float64
+        for i, (m, n, k) in enumerate(shapes):
+            cfg = table[dt][gen.cell_of(m, n, k)]
+            print(f"builtin choice dt={dt} shape={(m, n, k)} cell cfg={cfg}", flush=True)
+            A = synth.uniform_pm1((m, k), 700 + i)
+            B = synth.uniform_pm1((k, n), 800 + i)
+            if dt == mg.F32:
+                A, B = A.astype(np.float32).astype(np.float64), B.astype(np.float32).astype(np.float64)
+            tA, tB = torch.from_numpy(A).to(dev, tdt), torch.from_numpy(B).to(dev, tdt)
+            c1 = torch.full((m, n), float("nan"), device=dev, dtype=tdt)
+            c2 = torch.full((m, n), float("nan"), device=dev, dtype=tdt)
+            mg.gemm(tA, tB, c1, 1.0, 0.0)
+            mg.gemm(tA, tB, c2, 1.0, 0.0, cfg=cfg)
+            torch.cuda.synchronize()
+            assert torch.equal(c1, c2), (m, n, k)
+            rows = np.array([0, m // 2, m - 1])
+            ref = oracle.gemm_dot2(1.0, A[rows], B, nthreads=oracle.num_procs())
+            got = c1[torch.from_numpy(rows).to(dev)].cpu().double().numpy()
+            u = 2.0 ** -24 if dt == mg.F32 else 2.0 ** -53
+            bound = (k + 2) * u / (1 - (k + 2) * u) * (np.abs(A[rows]) @ np.abs(B))
+            assert np.all(np.abs(got - ref) <= bound), (m, n, k)
