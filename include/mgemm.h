@@ -106,11 +106,11 @@ MGEMM_API int32_t gemm(int64_t m, int64_t n, int64_t k, double alpha,
  * a hipStream_t; NULL: the current library stream).
  *
  * The library's choice (MGEMM_F64, MGEMM_F32): the largest preferred tile that
- * still gives enough work-groups for the m x n output; split-k below; and, for rows
- * the three-stage kernels cannot load (n, lda, ldb not multiples of 16 bytes, or A,
- * B not 16-byte aligned) with m, n, k in [64, 16384], the configuration measured
- * fastest on the tuner's shapes of the same (floor(log2 m), floor(log2 n),
- * floor(log2 k)) cell.
+ * still gives enough work-groups for the m x n output; split-k below; then, with
+ * m, n, k in [64, 16384], for rows the three-stage kernels cannot load (n, lda, ldb
+ * not multiples of 16 bytes, or A, B not 16-byte aligned), or where the preferred
+ * tile is a two-stage one, the configuration measured fastest on the tuner's shapes
+ * of the same row class and (floor(log2 m), floor(log2 n), floor(log2 k)) cell.
  *
  * Split-k (MGEMM_F64 and MGEMM_F32, cfg == NULL only): when the chosen tile
  * leaves fewer than about four work-groups per compute unit and k >= 512, k is

@@ -162,16 +162,20 @@ static const KernelEntry *find_entry(const KernelEntry *reg, int cnt, const mgem
     return nullptr;
 }
 
-// The configuration measured fastest for an m x n x k product whose rows the
-// three-stage kernels cannot load (choice_table.h: the tuner database's shapes of
-// the same log2 cell); NULL outside the table's range or for an unlisted cell.
-static const KernelEntry *measured_entry(int32_t dtype, int64_t m, int64_t n, int64_t k) {
+// The configuration measured fastest for an m x n x k product whose rows are
+// (rows16) or are not whole 16-byte loads (choice_table.h: the tuner database's
+// shapes of the same class and log2 cell); NULL outside the table's range or for
+// an unlisted cell.
+static const KernelEntry *measured_entry(int32_t dtype, bool rows16, int64_t m, int64_t n,
+                                         int64_t k) {
     constexpr int64_t lo = (int64_t)1 << CHOICE_LOG2_LO, hi = (int64_t)1 << CHOICE_LOG2_HI;
     if (m < lo || n < lo || k < lo || m > hi || n > hi || k > hi) return nullptr;
     auto lg = [](int64_t x) { int l = 0; while (x >> (l + 1)) ++l; return l; };
-    const ChoiceCell key = {(int8_t)dtype, (int8_t)lg(m), (int8_t)lg(n), (int8_t)lg(k)};
+    const ChoiceCell key = {(int8_t)dtype, (int8_t)(rows16 ? 1 : 0), (int8_t)lg(m),
+                            (int8_t)lg(n), (int8_t)lg(k)};
     auto less = [](const ChoiceCell &a, const ChoiceCell &b) {
         if (a.dtype != b.dtype) return a.dtype < b.dtype;
+        if (a.rows16 != b.rows16) return a.rows16 < b.rows16;
         if (a.lm != b.lm) return a.lm < b.lm;
         if (a.ln != b.ln) return a.ln < b.ln;
         return a.lk < b.lk;
@@ -329,10 +333,12 @@ int32_t gemm_ex(int64_t m, int64_t n, int64_t k, double alpha, const void *A, in
     if (!cfg) {
         const SplitPlan sp = splitk_plan(a, e, dtype);
         if (sp.S > 1) return run_splitk(e, a, dtype, al, sp, s);
-        // rows the three-stage kernels cannot load: the configuration measured
-        // fastest for shapes like this one (the preference list favours them)
-        if (!rows_whole_loads(a, dtype)) {
-            const KernelEntry *t = measured_entry(dtype, m, n, k);
+        // the configuration measured fastest for shapes like this one: always for
+        // rows the three-stage kernels cannot load (which the preference list
+        // favours), else where the list names a two-stage configuration
+        const bool rows16 = rows_whole_loads(a, dtype);
+        if (!rows16 || e->cfg.double_buffer != 2) {
+            const KernelEntry *t = measured_entry(dtype, rows16, m, n, k);
             if (t) e = t;
         }
     }

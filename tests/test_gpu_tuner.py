@@ -88,30 +88,47 @@ def test_chooser_database_then_model():
         assert err <= 1e-13
 
 
-def test_builtin_choice_for_rows_the_three_stage_kernels_cannot_load():
-    """gemm without a configuration, on held-out shapes whose n or k rules out the
-    three-stage kernels (and whose output is large enough that split-k does not
-    apply): it runs the configuration of the shape's cell in the library's measured
-    table, bit for bit the same as naming that configuration, and within the FP64 /
-    FP32 tolerances of the oracle on sampled rows."""
+def test_builtin_choice_runs_the_measured_configuration():
+    """gemm without a configuration, on held-out shapes whose output is large enough
+    that split-k does not apply: where the rows are not whole 16-byte loads, or the
+    preference list names a two-stage configuration, it runs the configuration of
+    the shape's cell in the library's measured table, bit for bit the same as naming
+    that configuration, and within the FP64 / FP32 tolerances of the oracle on
+    sampled rows."""
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     import oracle
     import synth
     from paper_1706_10086_amd.csrc import gen_choice_table as gen
+    sys_path_tests = os.path.dirname(os.path.abspath(__file__))
+    import importlib.util
+    spec = importlib.util.spec_from_file_location(
+        "choice_host", os.path.join(sys_path_tests, "test_choice_table_host.py"))
+    host = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(host)
     db = tune.load_compact(DB_PATH)
-    table = gen.build_table(db.records, set(tune.shape_set("train")))
+    tables = gen.build_tables(db.records, set(tune.shape_set("train")))
     dev = torch.device("cuda:0")
     for dt in (mg.F64, mg.F32):
-        shapes = [s for s in tune.shape_set("heldout")
-                  if gen.three_stage_ineligible(dt, s[1], s[2]) and 2.0 * s[0] * s[1] * s[2] < 4e10
-                  and (-(-s[0] // 128)) * (-(-s[1] // 64)) >= 256
-                  and gen.cell_of(*s) in table[dt]][:6]
-        assert len(shapes) == 6
+        picked = []
+        for whole in (False, True):
+            cand = []
+            for s in tune.shape_set("heldout"):
+                m, n, k = s
+                if gen.three_stage_ineligible(dt, n, k) == whole or 2.0 * m * n * k >= 4e10:
+                    continue
+                if (-(-m // 128)) * (-(-n // 64)) < 256:
+                    continue
+                if whole and host.pref_choice(dt, m, n)[5] == 2:
+                    continue
+                if gen.cell_of(m, n, k) in tables[int(whole)][dt]:
+                    cand.append(s)
+            picked += cand[:4]
+        assert len(picked) >= 6
         tdt = torch.float32 if dt == mg.F32 else torch.float64
-        for i, (m, n, k) in enumerate(shapes):
-            cfg = table[dt][gen.cell_of(m, n, k)]
-            print(f"builtin choice dt={dt} shape={(m, n, k)} cell cfg={cfg}", flush=True)
+        for i, (m, n, k) in enumerate(picked):
+            cfg = host.library_choice(tables, dt, m, n, k)
+            print(f"builtin choice dt={dt} shape={(m, n, k)} cfg={cfg}", flush=True)
             A = synth.uniform_pm1((m, k), 700 + i)
             B = synth.uniform_pm1((k, n), 800 + i)
             if dt == mg.F32:
