@@ -441,8 +441,8 @@ def leg_tuner(mg):
     log("bench: tuner leg, live re-timing of held-out shapes")
     live, builtin = live_recheck(mg, pred, table)
     return {"database": "paper_1706_10086_amd/data/tune_db.json.gz (MI355X sweep: 3000 train + "
-                        "500 held-out shapes, m,n,k log-uniform in [64,16384], FP64 and FP32, "
-                        "every registered configuration)",
+                        "500 held-out + 800 aligned shapes, m,n,k log-uniform in [64,16384], "
+                        "FP64 and FP32, every registered configuration)",
             "train_rows": len(dtr.shapes), "heldout_rows": len(dho.shapes),
             "train_s": round(t_train, 2), "mlp": mlp, "single_best_config": single,
             "mlp_top3_measured": top3, "regret_geomean": round(1.0 - mlp["geomean"], 4),

@@ -39,7 +39,7 @@ def db():
 
 
 def test_committed_table_matches_the_generator(db):
-    text = gen.render(gen.build_tables(db.records, set(tune.shape_set("train"))))
+    text = gen.render(gen.build_tables(db.records, gen.training_shapes()))
     with open(gen.OUT) as f:
         assert f.read() == text
 
@@ -57,7 +57,7 @@ def library_choice(tables, dt, m, n, k):
 
 @pytest.mark.parametrize("whole,floor", [(False, 0.95), (True, 0.90)])
 def test_table_beats_the_preference_list_on_held_out_shapes(db, whole, floor):
-    tables = gen.build_tables(db.records, set(tune.shape_set("train")))
+    tables = gen.build_tables(db.records, gen.training_shapes())
     held = set(tune.shape_set("heldout"))
     per_shape = collections.defaultdict(dict)
     for r in db.records:
@@ -77,7 +77,7 @@ def test_table_beats_the_preference_list_on_held_out_shapes(db, whole, floor):
 
 def test_cells_name_registered_configurations(db):
     import paper_1706_10086_amd as mg
-    tables = gen.build_tables(db.records, set(tune.shape_set("train")))
+    tables = gen.build_tables(db.records, gen.training_shapes())
     for w in (0, 1):
         for dt in (0, 1):
             reg = {c.as_tuple() for c in mg.configs(dt)}

@@ -107,7 +107,7 @@ def test_builtin_choice_runs_the_measured_configuration():
     host = importlib.util.module_from_spec(spec)
     spec.loader.exec_module(host)
     db = tune.load_compact(DB_PATH)
-    tables = gen.build_tables(db.records, set(tune.shape_set("train")))
+    tables = gen.build_tables(db.records, gen.training_shapes())
     dev = torch.device("cuda:0")
     for dt in (mg.F64, mg.F32):
         picked = []

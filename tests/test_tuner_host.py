@@ -112,7 +112,7 @@ def test_shipped_database_covers_the_registry():
     dts = {r["dtype"] for r in db.records}
     assert dts == {0, 1}
     n_shapes = len({(r["dtype"], r["m"], r["n"], r["k"]) for r in db.records})
-    assert n_shapes == 7000
+    assert n_shapes == 8600          # train + held-out + aligned, both dtypes
 
 
 def test_raw_grid_and_validity_rules():
