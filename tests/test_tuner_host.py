@@ -162,3 +162,13 @@ def test_batch_rules_map_every_shape_to_a_registered_configuration():
         # a mixture gives thin problems the smallest tile and the rest the 64x64 one
         mix = next(r for n_, r in rules.items() if n_.startswith("min(m,n) <= 32"))
         assert mix(31, 1000, 17)[:2] == (32, 32) and mix(300, 700, 64)[:2] == (64, 64)
+
+
+def test_aligned_shape_set():
+    al = tune.shape_set("aligned")
+    assert len(al) == 800 and len(set(al)) == 800
+    assert all(x % 4 == 0 and 64 <= x <= 16384 for s in al for x in s)
+    assert not set(al) & (set(tune.shape_set("train")) | set(tune.shape_set("heldout")))
+    assert tune.shape_set("aligned")[:7] == al[:7]
+    with pytest.raises(ValueError):
+        tune.shape_set("other")
