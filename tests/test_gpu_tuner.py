@@ -100,12 +100,7 @@ def test_builtin_choice_runs_the_measured_configuration():
     import oracle
     import synth
     from paper_1706_10086_amd.csrc import gen_choice_table as gen
-    sys_path_tests = os.path.dirname(os.path.abspath(__file__))
-    import importlib.util
-    spec = importlib.util.spec_from_file_location(
-        "choice_host", os.path.join(sys_path_tests, "test_choice_table_host.py"))
-    host = importlib.util.module_from_spec(spec)
-    spec.loader.exec_module(host)
+    import choice_rule as host
     db = tune.load_compact(DB_PATH)
     tables = gen.build_tables(db.records, gen.training_shapes())
     dev = torch.device("cuda:0")
