@@ -345,7 +345,7 @@ def sweep_set(shapes, dtype, db: DB, reps=2, abandon=2.0, log=print, every=25):
 
 # ---------------------------------------------------------------------------
 # Batched plans: which tile configuration each problem of a batch runs with.
-# The problems of a plan share the GPU, so a choice is judged by timing the
+# The problems of a plan share the GPU, so a choice is scored by timing the
 # whole captured plan, not problem by problem.
 # ---------------------------------------------------------------------------
 def batch_rules(dtype: int) -> dict:
