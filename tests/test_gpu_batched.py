@@ -171,6 +171,42 @@ def test_uneven_batch_2048(dev, orc):
     plan.destroy()
 
 
+def test_uneven_batch_2048_fp32(dev, orc):
+    """The FP32 variant of the batched workload: the plan bitwise against per-problem
+    gemm_ex with the 64 x 64 x 16 configuration, and sampled problems within
+    gamma_{k+2} (u = 2^-24) of the oracle on the same float inputs."""
+    say("batched 2048 uneven fp32: building inputs on the device")
+    cnt = 2048
+    ms = synth.log_uniform_int(cnt, 4001, 16, 1024)
+    ns = synth.log_uniform_int(cnt, 4002, 16, 1024)
+    ks = synth.log_uniform_int(cnt, 4003, 16, 1024)
+    g = torch.Generator(device=dev)
+    g.manual_seed(4005)
+    As = [torch.rand((int(m), int(k)), device=dev, dtype=torch.float32, generator=g) * 2 - 1
+          for m, k in zip(ms, ks)]
+    Bs = [torch.rand((int(k), int(n)), device=dev, dtype=torch.float32, generator=g) * 2 - 1
+          for k, n in zip(ks, ns)]
+    Cs = [torch.zeros((int(m), int(n)), device=dev, dtype=torch.float32) for m, n in zip(ms, ns)]
+    Cr = [torch.zeros_like(c) for c in Cs]
+    plan = mg.BatchedPlan(As, Bs, Cs, 1.0, 0.0)
+    say(f"  plan {plan.info()}")
+    plan.execute()
+    c64 = [c for c in mg.configs(mg.F32) if (c.bm, c.bn, c.bk, c.waves) == (64, 64, 16, 4)][0]
+    for a, b, c in zip(As, Bs, Cr):
+        mg.gemm(a, b, c, 1.0, 0.0, cfg=c64)
+    torch.cuda.synchronize()
+    for i in range(cnt):
+        assert torch.equal(Cs[i], Cr[i]), i
+    u = 2.0 ** -24
+    for i in (0, 1, 777, 2047):
+        A, B = As[i].cpu().double().numpy(), Bs[i].cpu().double().numpy()
+        ref = orc.gemm_dot2(1.0, A, B)
+        k = A.shape[1]
+        bound = (k + 2) * u / (1 - (k + 2) * u) * (np.abs(A) @ np.abs(B))
+        assert np.all(np.abs(Cs[i].cpu().double().numpy() - ref) <= bound), i
+    plan.destroy()
+
+
 def test_plan_without_tile_map(dev, orc):
     """A problem with 2^20 + 1 tile rows (m = 2^25 + 5 with 32-row tiles) does not fit
     the tile map's fields, so the plan's kernels find each tile's problem by binary
