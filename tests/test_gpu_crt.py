@@ -155,12 +155,12 @@ def test_deterministic(dev):
     assert torch.equal(outs[0], outs[1])
 
 
-def test_full_size_sampled_rows(dev, orc):
-    """N = 8192 wide-range (the split-precision benchmark workload): sampled rows
-    recomputed by the oracle, bitwise."""
-    n = 8192
+@pytest.mark.parametrize("n", [4096, 8192])
+def test_full_size_sampled_rows(dev, orc, n):
+    """N = 4096 and 8192 wide-range (the split-precision benchmark workload): sampled
+    rows recomputed by the oracle, bitwise."""
     say(f"crt full size n={n}: generating inputs")
-    sa, sb, _ = synth.seeds_for(3, 13)
+    sa, sb, _ = synth.seeds_for(3, int(np.log2(n)))
     A = synth.wide_range((n, n), sa)
     B = synth.wide_range((n, n), sb)
     tA, tB = to_dev(A, dev), to_dev(B, dev)
