@@ -61,10 +61,40 @@ def parse():
     ap.add_argument("--no-extras", action="store_true", help="only the FP64 headline leg")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--leg", choices=["parity", "sweep", "split", "batched", "batched_plan", "tuner",
-                                       "memory"],
+                                       "memory", "copy"],
                     default=None,
-                    help="run only this extra leg and print its JSON (for profiling runs)")
+                    help="run only this extra leg and print its JSON (for profiling runs; "
+                         "'copy' is the calibration workload of the traffic counters)")
+    ap.add_argument("--copy-mib", type=int, default=1024, help="copy leg: MiB per copy")
+    ap.add_argument("--copy-reps", type=int, default=3, help="copy leg: number of copies")
     return ap.parse_args()
+
+
+def cpu_model() -> str:
+    """The host CPU's model name (Linux /proc/cpuinfo), or 'unknown'."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def leg_copy(torch, dev, mib=1024, reps=3):
+    """Calibration workload for the HBM traffic counters: a device-to-device copy
+    of a known number of bytes (torch's copy kernel), ``reps`` times.  Run under
+    rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE), the reading per copied byte
+    scales the same counters of the GEMM kernels to bytes."""
+    n = mib * 1024 * 1024 // 8
+    src = torch.rand(n, device=dev, dtype=torch.float64)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    return {"bytes_per_copy": 8 * n, "copies": reps}
 
 
 def log(msg):
@@ -108,7 +138,7 @@ def cpu_baseline(n, A, B, C, budget_s):
     oracle.gemm_f64(1.0, a1, b1, 0.0, None, nthreads=1)
     t1 = time.perf_counter() - t1
     return {"value": round(flops / dt / 1e12, 5), "unit": "TFLOP/s", "cores": cores,
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": cpu_model(),
             "sample": f"first {rows} of {n} rows of the N={n} FP64 product "
                       f"({flops / 1e9:.1f} GFLOP in {dt:.1f} s, OpenMP over rows)",
             "single_thread_n1024_s": round(t1, 3),
@@ -474,7 +504,8 @@ def main():
                 "batched": lambda: leg_batched(mg, torch, dev),
                 "batched_plan": lambda: leg_batched(mg, torch, dev, plan_only=True),
                 "tuner": lambda: leg_tuner(mg),
-                "memory": lambda: leg_memory(mg, torch, dev)}
+                "memory": lambda: leg_memory(mg, torch, dev),
+                "copy": lambda: leg_copy(torch, dev, args.copy_mib, args.copy_reps)}
         print(json.dumps({args.leg: legs[args.leg]()}), flush=True)
         return 0
     log(f"bench: generating N={n} inputs")
@@ -512,6 +543,7 @@ def main():
     tflops = flops / (ms * 1e-3) / 1e12
     kern_ms = float(np.mean(per))
     best_ms = float(np.min(per))
+    median_ms = float(np.median(per))
 
     # accuracy of this run against the oracle on sampled rows: C_s = A B + C_{s-1}
     import oracle
@@ -554,6 +586,8 @@ def main():
                    "parallelism": "single GPU"},
         "pct_peak": round(100.0 * tflops / PEAK_F64_TFLOPS, 2),
         "best_step_tflops": round(flops / (best_ms * 1e-3) / 1e12, 3),
+        "median_ms_per_step": round(median_ms, 4),
+        "median_step_tflops": round(flops / (median_ms * 1e-3) / 1e12, 3),
         "wall_s": round(wall, 3),
         "sampled_rel_err_vs_oracle": err,
         "roofline": {"bound": "mfma", "achieved": round(flops / (kern_ms * 1e-3) / 1e12, 3),

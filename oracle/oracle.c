@@ -30,7 +30,10 @@
  *                      products, one rounding to FP64 (Ozaki, Ogita, Oishi, Rump,
  *                      "Error-free transformations of matrix multiplication ...",
  *                      Numer. Algorithms 59, 2012).
- *   orc_mlp_*       -- FP64 forward/backward/Adam of the 3-layer MLP cost model.
+ *   orc_crt_gemm    -- the modular-integer emulation (Ozaki scheme II) written as
+ *                      its plain definition: operands truncated per row / column,
+ *                      their exact product summed in 128-bit integers, one rounding.
+ * The FP64 model of the MLP cost model is not here: it is oracle/mlp.py (numpy).
  */
 #include <math.h>
 #include <stdint.h>

@@ -312,15 +312,19 @@ class BatchedPlan:
     ``cfgs``: None (library choice) or one Cfg / tuple per problem."""
 
     def __init__(self, As, Bs, Cs, alphas=1.0, betas=0.0, dtype=None, cfgs=None, stream=None):
+        self.handle = ctypes.c_void_p()
         self.dtype = dtype_of(As[0]) if dtype is None and As else (dtype or F64)
         if self.dtype in (F64, F32):
             _check_operands(self.dtype, *As, *Bs, *Cs)
+        # the plan reads A, B and writes C at every execution through the raw
+        # addresses it keeps, so the tensors themselves are held until destroy():
+        # memory the caching allocator reused would otherwise be written
+        self._tensors = (list(As), list(Bs), list(Cs))
         self._arrs = _BatchArrays(As, Bs, Cs, alphas, betas)
         cfg_arr = None
         if cfgs is not None:
             cfg_arr = (Cfg * len(cfgs))(*[c if isinstance(c, Cfg) else Cfg(*c) for c in cfgs])
         self._cfgs = cfg_arr
-        self.handle = ctypes.c_void_p()
         _check(lib().gemm_batched_plan_create(
             *self._arrs.args(), self.dtype,
             ctypes.cast(cfg_arr, ctypes.c_void_p).value if cfg_arr is not None else None,
@@ -341,6 +345,7 @@ class BatchedPlan:
         if self.handle:
             lib().gemm_batched_plan_destroy(self.handle)
             self.handle = ctypes.c_void_p()
+        self._tensors = None
 
     def __del__(self):
         try:
@@ -378,6 +383,13 @@ def _mlp_lib():
     return L
 
 
+def mlp_rows_check(name: str, shape: tuple, cols: int, rows: int | None = None) -> None:
+    """Raises ValueError unless ``shape`` is (rows, cols) (any rows when None)."""
+    if len(shape) != 2 or shape[1] != cols or (rows is not None and shape[0] != rows):
+        want = f"({'rows' if rows is None else rows}, {cols})"
+        raise ValueError(f"{name} has shape {shape}, expected {want}")
+
+
 class MLP:
     """The library's FP32 MLP cost model (see mlp_* in mgemm.h).  Parameters are
     exchanged as flat float32 numpy arrays; data as float32 torch tensors."""
@@ -407,9 +419,32 @@ class MLP:
         a = np.ascontiguousarray(params, dtype=np.float32)
         _check(_mlp_lib().mlp_set_params(self.handle, a.ctypes.data))
 
+    def _device_rows(self, name, t, cols, rows=None):
+        """t as a contiguous float32 tensor on the current GPU, checked to be
+        rows x cols (rows taken from t when None): the C calls read rows*cols
+        floats through a bare device pointer."""
+        import torch
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{name}: torch tensor expected")
+        dev = torch.cuda.current_device() if torch.cuda.is_available() else None
+        if not t.is_cuda or t.device.index != dev:
+            raise ValueError(f"{name} must live on the current GPU")
+        mlp_rows_check(name, tuple(t.shape), cols, rows)
+        return t.contiguous().float()
+
+    @staticmethod
+    def _after_torch():
+        """The library's calls run on its own stream: wait for the work torch
+        queued (e.g. the conversions above) before they read the tensors."""
+        import torch
+        torch.cuda.current_stream().synchronize()
+
     def set_data(self, X, T, M) -> None:
-        self._data = tuple(t.contiguous().float() for t in (X, T, M))
-        X, T, M = self._data
+        X = self._device_rows("X", X, self.dims[0])
+        T = self._device_rows("T", T, self.dims[2], X.shape[0])
+        M = self._device_rows("M", M, self.dims[2], X.shape[0])
+        self._data = (X, T, M)
+        self._after_torch()
         _check(_mlp_lib().mlp_set_data(self.handle, X.shape[0], X.data_ptr(), T.data_ptr(),
                                        M.data_ptr()))
 
@@ -428,16 +463,18 @@ class MLP:
 
     def forward(self, X):
         import torch
-        X = X.contiguous().float()
+        X = self._device_rows("X", X, self.dims[0])
         Y = torch.empty((X.shape[0], self.dims[2]), device=X.device, dtype=torch.float32)
+        self._after_torch()
         _check(_mlp_lib().mlp_forward(self.handle, X.shape[0], X.data_ptr(), Y.data_ptr()))
         return Y
 
     def predict(self, X, M):
         import torch
-        X = X.contiguous().float()
-        M = M.contiguous().float()
+        X = self._device_rows("X", X, self.dims[0])
+        M = self._device_rows("M", M, self.dims[2], X.shape[0])
         idx = torch.empty((X.shape[0],), device=X.device, dtype=torch.int32)
+        self._after_torch()
         _check(_mlp_lib().mlp_predict(self.handle, X.shape[0], X.data_ptr(), M.data_ptr(),
                                       idx.data_ptr()))
         return idx

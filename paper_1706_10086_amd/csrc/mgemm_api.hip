@@ -316,16 +316,16 @@ int32_t gemm_ex(int64_t m, int64_t n, int64_t k, double alpha, const void *A, in
     g_err.clear();
     int32_t rc = check_args(m, n, k, alpha, A, lda, B, ldb, C, ldc, dtype);
     if (rc) return rc;
+    // whether a call is valid does not depend on the values of alpha or beta
+    if (dtype >= MGEMM_SPLIT_BF16 && cfg)
+        return set_error(-13, "split dtypes take no tile configuration");
     hipStream_t s = stream ? (hipStream_t)stream : g_stream;
     if (m == 0 || n == 0) return 0;
     if (k == 0 || alpha == 0.0) {
         return scale_c(dtype == MGEMM_F32 ? MGEMM_F32 : MGEMM_F64, m, n, beta, C, ldc, s);
     }
     GemmArgs a{m, n, k, alpha, beta, A, lda, B, ldb, C, ldc};
-    if (dtype >= MGEMM_SPLIT_BF16) {
-        if (cfg) return set_error(-13, "split dtypes take no tile configuration");
-        return split_gemm(a, dtype, s);
-    }
+    if (dtype >= MGEMM_SPLIT_BF16) return split_gemm(a, dtype, s);
     int32_t err = 0;
     const KernelEntry *e = choose_entry(dtype, m, n, cfg, &err);
     if (!e) return err;

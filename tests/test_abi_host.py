@@ -80,6 +80,16 @@ def test_unregistered_config_rejected(L):
     assert mg.gemm_ex_raw(4, 4, 4, 1.0, P, 4, P * 4, 4, 0.0, P * 2, 4, 0, bad, None) == -13
 
 
+@pytest.mark.parametrize("dtype", [mg.SPLIT_BF16, mg.SPLIT_FP8, mg.SPLIT_INT8, mg.CRT_INT8])
+@pytest.mark.parametrize("alpha,k", [(1.0, 4), (0.0, 4), (1.0, 0)])
+def test_split_dtype_with_config_rejected_whatever_alpha(L, dtype, alpha, k):
+    # the check comes before the alpha == 0 / k == 0 quick return, so the verdict on
+    # a call does not depend on the value of alpha
+    cfg = mg.Cfg(64, 64, 16, 4, 2, 1, 0)
+    assert mg.gemm_ex_raw(4, 4, k, alpha, P, 4, P * 4, 4, 0.0, P * 2, 4, dtype, cfg, None) == -13
+    assert "split dtypes" in mg.last_error()
+
+
 def test_config_registry(L):
     for dt in (mg.F64, mg.F32):
         cs = mg.configs(dt)

@@ -71,21 +71,25 @@ def test_chooser_database_then_model():
     shape the model's prediction; the product is correct either way."""
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
+    import oracle
+    import synth
     from paper_1706_10086_amd import choose
     ch = choose.ConfigChooser()
     seen = tune.shape_set("heldout")[0]
-    for (m, n, k), want in ((seen, "database"), ((333, 517, 271), "model")):
+    for i, ((m, n, k), want) in enumerate(((seen, "database"), ((333, 517, 271), "model"))):
         print(f"chooser shape {(m, n, k)}", flush=True)
-        g = torch.Generator().manual_seed(m + n + k)
-        A = torch.rand((m, k), generator=g, dtype=torch.float64)
-        B = torch.rand((k, n), generator=g, dtype=torch.float64)
+        A = synth.uniform_pm1((m, k), 610 + 2 * i)
+        B = synth.uniform_pm1((k, n), 611 + 2 * i)
         C = torch.zeros((m, n), dtype=torch.float64, device="cuda")
-        _, source = choose.tuned_gemm(A.cuda(), B.cuda(), C, chooser=ch)
+        _, source = choose.tuned_gemm(torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda(), C,
+                                      chooser=ch)
         torch.cuda.synchronize()
         assert source == want
-        ref = A @ B
-        err = float(torch.linalg.norm(C.cpu() - ref) / torch.linalg.norm(ref))
-        assert err <= 1e-13
+        ref = oracle.gemm_f64(1.0, A, B, 0.0, None, nthreads=oracle.num_procs())
+        got = C.cpu().numpy()
+        assert float(np.linalg.norm(got - ref) / np.linalg.norm(ref)) <= 1e-13
+        u = 2.0 ** -53
+        assert np.all(np.abs(got - ref) <= 2 * (k + 2) * u / (1 - (k + 2) * u) * (np.abs(A) @ np.abs(B)))
 
 
 def test_builtin_choice_runs_the_measured_configuration():
