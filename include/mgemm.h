@@ -39,7 +39,9 @@
  *          dtype, or a NULL pointer whose matrix is non-empty.  Positive codes are
  *          run-time errors: MGEMM_ERR_HIP (text in mgemm_last_error()),
  *          MGEMM_ERR_NOMEM, MGEMM_ERR_NONFINITE (split paths: NaN or Inf in A or
- *          B), MGEMM_ERR_NOCONFIG, MGEMM_ERR_PLAN.  On any error C is untouched.
+ *          B), MGEMM_ERR_NOCONFIG, MGEMM_ERR_PLAN, MGEMM_ERR_MODEL (a cost-model
+ *          file that cannot be read, is corrupt or does not match the library, or
+ *          no model loaded).  On any error C is untouched.
  * Threads  Calls may come from several host threads; the error text is
  *          per thread.  Concurrent calls that share a split-path workspace on
  *          one device are serialised by the library.
@@ -70,7 +72,8 @@ enum {
     MGEMM_ERR_NOMEM = 2,
     MGEMM_ERR_NONFINITE = 3,
     MGEMM_ERR_NOCONFIG = 4,
-    MGEMM_ERR_PLAN = 5
+    MGEMM_ERR_PLAN = 5,
+    MGEMM_ERR_MODEL = 6
 };
 
 /*
@@ -111,6 +114,8 @@ MGEMM_API int32_t gemm(int64_t m, int64_t n, int64_t k, double alpha,
  * not multiples of 16 bytes, or A, B not 16-byte aligned), or where the preferred
  * tile is a two-stage one, the configuration measured fastest on the tuner's shapes
  * of the same row class and (floor(log2 m), floor(log2 n), floor(log2 k)) cell.
+ * With a cost model loaded (mgemm_model_load), its prediction replaces the last
+ * two steps.
  *
  * Split-k (MGEMM_F64 and MGEMM_F32, cfg == NULL only): when the chosen tile
  * leaves fewer than about four work-groups per compute unit and k >= 512, k is
@@ -170,8 +175,9 @@ MGEMM_API int32_t gemm_batched(int64_t count, const int64_t *m, const int64_t *n
                                int32_t dtype);
 
 /* Builds a reusable plan for one batched launch: problems are grouped by tile
- * configuration (cfgs[i]; when cfgs is NULL every problem uses the registered
- * 64x64x16 four-wave configuration); per group one persistent kernel takes C
+ * configuration (cfgs[i], argument 14: a registered configuration with the
+ * MGEMM_CFG_BATCHED flag, else -14; when cfgs is NULL every problem uses the
+ * registered 64x64x16 four-wave configuration); per group one persistent kernel takes C
  * tiles from per-XCD atomic work lists, each tile running the code path of its
  * problem's row alignment; all groups are captured into one HIP graph.  The plan keeps the problem
  * descriptors (pointers, sizes, alpha, beta) -- the matrices must stay valid and
@@ -211,7 +217,7 @@ MGEMM_API int32_t gemm_batched_plan_info(void *plan, int32_t *buckets, int64_t *
  * Parameters are one flat FP32 vector W1 (hidden x in), b1, W2 (hidden x hidden),
  * b2, W3 (out x hidden), b3, row-major.  Host arrays are marked (host), the rest
  * are device pointers.  All calls run on the library's current stream and return
- * after it has finished.  Dimensions are limited to 1..256.
+ * after it has finished.  Dimensions are limited to 1..4096.
  */
 /* Creates a model with the given initial parameters (host, mlp_param_count
  * floats); Adam moments start at zero.  *mlp receives the handle. */
@@ -244,6 +250,48 @@ MGEMM_API int32_t mlp_predict(void *mlp, int64_t rows, const float *X, const flo
  * MGEMM_ERR_HIP if that wait reported an error (the model is freed anyway). */
 MGEMM_API int32_t mlp_destroy(void *mlp);
 
+/* Saves a trained network as a tile-configuration model file that
+ * mgemm_model_load reads: its parameters (copied from the device), the feature
+ * scaling it was trained with and the configuration each output stands for.
+ *   path       file to write (replaced);
+ *   out_dtype  (host, out entries) dtype of each output, MGEMM_F64 or MGEMM_F32;
+ *   out_cfg    (host, out entries) the registered configuration of each output;
+ *   feat_mean, feat_std  (host, 6 doubles each, std > 0) the features x = [log2 m,
+ *              log2 n, log2 k, dtype == MGEMM_F64, == MGEMM_F32, == MGEMM_SPLIT_BF16]
+ *              enter the network as (x - mean) / std rounded to float.
+ * The network must have 6 inputs.  Every value is written as a C99 hexadecimal
+ * float (exact), followed by an FNV-1a checksum of the text.  Returns 0; -1..-6
+ * for a NULL argument; MGEMM_ERR_MODEL (not 6 inputs, an output naming a
+ * configuration this library does not register, or a failed write). */
+MGEMM_API int32_t mlp_save(void *mlp, const char *path, const int32_t *out_dtype,
+                           const mgemm_cfg *out_cfg, const double *feat_mean,
+                           const double *feat_std);
+
+/* Loads the learned tile-configuration model (a file from mlp_save) for this
+ * process, replacing any model loaded before; path NULL unloads.  The paper
+ * searches its tuning parameters exhaustively per architecture (Sec. 3, Tab. 4)
+ * and names that tuning as the cost that grows with the parameters (Sec. 6); with
+ * a model loaded, gemm_ex with cfg == NULL (MGEMM_F64, MGEMM_F32) runs the
+ * model's prediction for the shape instead of the built-in table, except where
+ * the built-in choice cuts k (split-k: no model output stands for it).  The
+ * first such call for a shape evaluates the network on the current device with
+ * the library's kernels and waits for it (calls on a stream being captured into a
+ * graph use a prediction only if one is already cached);
+ * later calls reuse the cached prediction.  The file is read and checked on the
+ * host: returns 0, or MGEMM_ERR_MODEL when it cannot be read, its checksum or
+ * syntax is wrong, it does not have 6 inputs, or an output names a configuration
+ * this library does not register (the model loaded before stays loaded then). */
+MGEMM_API int32_t mgemm_model_load(const char *path);
+
+/* The loaded model's configuration for an m x n x k product of dtype (the output
+ * of that dtype with the largest predicted value, lowest index on ties),
+ * evaluated by the library's HIP kernels on the current device (the call waits
+ * for them; predictions are cached per shape).  Returns 0; -1..-3 (m, n or k
+ * below 1), -4 (the model has no output for dtype), -5 (out NULL);
+ * MGEMM_ERR_MODEL (no model loaded). */
+MGEMM_API int32_t mgemm_model_predict(int64_t m, int64_t n, int64_t k, int32_t dtype,
+                                      mgemm_cfg *out);
+
 /* Sets the stream used when a call passes NULL; returns 0. */
 MGEMM_API int32_t mgemm_set_stream(void *stream);
 
@@ -256,6 +304,17 @@ MGEMM_API int32_t mgemm_config_count(int32_t dtype);
 
 /* Copies registered configuration i of dtype into *out; 0 or -2 / -3. */
 MGEMM_API int32_t mgemm_config_get(int32_t dtype, int32_t i, mgemm_cfg *out);
+
+/* What registered configuration i of dtype runs in, as bits: MGEMM_CFG_GEMM
+ * (gemm_ex with this cfg), MGEMM_CFG_BATCHED (batched plans accept it),
+ * MGEMM_CFG_SPLITK (the built-in choice may cut k with it).  Every registered
+ * configuration runs in gemm_ex; the tuning-grid configurations (the paper's
+ * tile-size search of Sec. 3, Tab. 4, widened to the GPU's parameters) only there.
+ * Returns the bits, -1 (bad dtype) or -2 (i out of range). */
+#define MGEMM_CFG_GEMM 1
+#define MGEMM_CFG_BATCHED 2
+#define MGEMM_CFG_SPLITK 4
+MGEMM_API int32_t mgemm_config_flags(int32_t dtype, int32_t i);
 
 /* Frees the library-owned workspace of the current device (split dtypes and
  * split-k) once the work that last used it has finished; 0 on success,

@@ -33,7 +33,9 @@ EXPORTED = [
     "mgemm_config_get", "mgemm_release_workspace", "mgemm_probe_mfma", "mgemm_probe_mfma_raw",
     "gemm_batched", "gemm_batched_plan_create", "gemm_batched_plan_execute",
     "gemm_batched_plan_destroy", "gemm_batched_plan_info", "mgemm_host_alloc", "mgemm_host_free",
+    "mgemm_config_flags",
 ]
+CFG_GEMM, CFG_BATCHED, CFG_SPLITK = 1, 2, 4
 
 
 class MgemmNotBuilt(RuntimeError):
@@ -87,6 +89,8 @@ def lib():
     L.mgemm_config_count.restype = i32
     L.mgemm_config_get.argtypes = [i32, i32, ctypes.POINTER(Cfg)]
     L.mgemm_config_get.restype = i32
+    L.mgemm_config_flags.argtypes = [i32, i32]
+    L.mgemm_config_flags.restype = i32
     L.mgemm_release_workspace.argtypes = []
     L.mgemm_release_workspace.restype = i32
     L.mgemm_probe_mfma.argtypes = [i32, p, p, p, p]
@@ -171,13 +175,17 @@ class HostBuffer:
             pass
 
 
-def configs(dtype: int) -> list[Cfg]:
+def configs(dtype: int, need: int = 0) -> list[Cfg]:
+    """The registered configurations of dtype, in registry order; with ``need``
+    (CFG_BATCHED, CFG_SPLITK bits) only those that take part in all of it."""
     L = lib()
     n = L.mgemm_config_count(dtype)
     if n < 0:
         raise MgemmError(n, "bad dtype")
     out = []
     for i in range(n):
+        if need and (L.mgemm_config_flags(dtype, i) & need) != need:
+            continue
         c = Cfg()
         _check(L.mgemm_config_get(dtype, i, ctypes.byref(c)))
         out.append(c)
@@ -356,7 +364,8 @@ class BatchedPlan:
 
 MLP_SYMBOLS = ["mlp_create", "mlp_param_count", "mlp_set_params", "mlp_get_params",
                "mlp_set_data", "mlp_loss_grad", "mlp_train", "mlp_forward", "mlp_predict",
-               "mlp_destroy"]
+               "mlp_destroy", "mlp_save", "mgemm_model_load", "mgemm_model_predict"]
+ERR_MODEL = 6
 EXPORTED += MLP_SYMBOLS
 
 
@@ -376,11 +385,27 @@ def _mlp_lib():
     L.mlp_forward.argtypes = [p, i64, p, p]
     L.mlp_predict.argtypes = [p, i64, p, p, p]
     L.mlp_destroy.argtypes = [p]
+    L.mlp_save.argtypes = [p, ctypes.c_char_p, p, p, p, p]
+    L.mgemm_model_load.argtypes = [ctypes.c_char_p]
+    L.mgemm_model_predict.argtypes = [i64, i64, i64, i32, ctypes.POINTER(Cfg)]
     for n in ("mlp_create", "mlp_set_params", "mlp_get_params", "mlp_set_data", "mlp_loss_grad",
-              "mlp_train", "mlp_forward", "mlp_predict", "mlp_destroy"):
+              "mlp_train", "mlp_forward", "mlp_predict", "mlp_destroy", "mlp_save",
+              "mgemm_model_load", "mgemm_model_predict"):
         getattr(L, n).restype = i32
     L._mlp_ready = True
     return L
+
+
+def model_load(path) -> None:
+    """Loads a tile-configuration model file (mgemm_model_load); None unloads."""
+    _check(_mlp_lib().mgemm_model_load(None if path is None else os.fsencode(path)))
+
+
+def model_predict(m: int, n: int, k: int, dtype: int = F64) -> Cfg:
+    """The loaded model's configuration for an m x n x k product (mgemm_model_predict)."""
+    c = Cfg()
+    _check(_mlp_lib().mgemm_model_predict(int(m), int(n), int(k), int(dtype), ctypes.byref(c)))
+    return c
 
 
 def mlp_rows_check(name: str, shape: tuple, cols: int, rows: int | None = None) -> None:
@@ -478,6 +503,22 @@ class MLP:
         _check(_mlp_lib().mlp_predict(self.handle, X.shape[0], X.data_ptr(), M.data_ptr(),
                                       idx.data_ptr()))
         return idx
+
+    def save(self, path, table, mean, std) -> None:
+        """Writes the network as a tile-configuration model file (mlp_save):
+        ``table`` lists (dtype, configuration tuple) per output, ``mean`` and
+        ``std`` the 6 feature scales."""
+        if len(table) != self.dims[2]:
+            raise ValueError("one (dtype, configuration) per output expected")
+        dts = np.ascontiguousarray([d for d, _ in table], dtype=np.int32)
+        cfgs = (Cfg * len(table))(*[Cfg(*c) for _, c in table])
+        mu = np.ascontiguousarray(mean, dtype=np.float64)
+        sd = np.ascontiguousarray(std, dtype=np.float64)
+        if mu.shape != (6,) or sd.shape != (6,):
+            raise ValueError("6 feature means and standard deviations expected")
+        _check(_mlp_lib().mlp_save(self.handle, os.fsencode(path), dts.ctypes.data,
+                                   ctypes.cast(cfgs, ctypes.c_void_p).value, mu.ctypes.data,
+                                   sd.ctypes.data))
 
     def destroy(self) -> None:
         if self.handle:

@@ -198,8 +198,14 @@ int32_t gemm_batched_plan_create(int64_t count, const int64_t *m, const int64_t 
         // (28.2 vs 18.8 TFLOP/s with the single-GEMM choice, MI355X)
         const KernelEntry *e =
             choose_entry(dtype, m[i], n[i], cfgs ? &cfgs[i] : &kBatchedDefault, &err);
-        if (!e) {
+        if (!e || !e->batched) {
             plan_free(p);
+            if (cfgs)
+                return set_error(-14, "problem %lld: configuration %dx%dx%d w%d e%d d%d o%d is %s",
+                                 (long long)i, cfgs[i].bm, cfgs[i].bn, cfgs[i].bk, cfgs[i].waves,
+                                 cfgs[i].elems_per_thread, cfgs[i].double_buffer,
+                                 cfgs[i].occupancy,
+                                 e ? "not available in batched plans" : "not registered");
             return err ? err : set_error(MGEMM_ERR_NOCONFIG, "problem %lld: no configuration",
                                          (long long)i);
         }

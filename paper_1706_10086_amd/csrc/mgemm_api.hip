@@ -228,6 +228,26 @@ const KernelEntry *choose_entry(int32_t dtype, int64_t m, int64_t n, const mgemm
 }
 
 int32_t split_gemm(const GemmArgs &a, int32_t dtype, hipStream_t s);
+int32_t model_choose(int32_t dtype, int64_t m, int64_t n, int64_t k, bool may_launch,
+                     mgemm_cfg *out);
+
+// Whether cfg is in dtype's registry.
+bool cfg_registered(int32_t dtype, const mgemm_cfg &c) {
+    int cnt = 0;
+    const KernelEntry *reg = registry(dtype, &cnt);
+    return reg && find_entry(reg, cnt, c) != nullptr;
+}
+
+// Whether work enqueued on s is being captured into a graph (then nothing may be
+// launched and waited for on another stream); unknown counts as capturing.
+static bool capturing(hipStream_t s) {
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &st) != hipSuccess) {
+        (void)hipGetLastError();
+        return true;
+    }
+    return st != hipStreamCaptureStatusNone;
+}
 
 // Split-k for the built-in choice: when that fell back to a 64 x 64 or 32 x 32
 // tile and still leaves fewer than about four work-groups per compute unit, k is
@@ -293,26 +313,29 @@ static SplitPlan splitk_plan(const GemmArgs &a, const KernelEntry *e, int32_t dt
     return sp;
 }
 
+// The partial products and their reduction, in W (the caller's buffer of at least
+// S*m*n elements).
+static int32_t launch_splitk_into(const KernelEntry *e, const GemmArgs &a, int32_t dtype,
+                                  bool al, const SplitPlan &sp, uint8_t *W, hipStream_t s) {
+    hipError_t he = sp.pipe ? launch_pipe_splitk(a, dtype, sp.S, sp.kc, W, s)
+                            : e->splitk[al ? 0 : 1](a, sp.S, sp.kc, W, s);
+    if (he == hipSuccess) he = splitk_reduce(dtype, W, sp.S, a, s);
+    return he == hipSuccess ? 0 : hip_error(he, "split-k launch");
+}
+
+// Split-k with its planes in the library workspace (grown on demand).
 static int32_t run_splitk(const KernelEntry *e, const GemmArgs &a, int32_t dtype, bool al,
                           const SplitPlan &sp, hipStream_t s) {
     const size_t es = dtype == MGEMM_F32 ? 4 : 8;
     return with_workspace((size_t)sp.S * a.m * a.n * es, s, [&](uint8_t *W) -> int32_t {
-        hipError_t he = sp.pipe ? launch_pipe_splitk(a, dtype, sp.S, sp.kc, W, s)
-                                : e->splitk[al ? 0 : 1](a, sp.S, sp.kc, W, s);
-        if (he == hipSuccess) he = splitk_reduce(dtype, W, sp.S, a, s);
-        return he == hipSuccess ? 0 : hip_error(he, "split-k launch");
+        return launch_splitk_into(e, a, dtype, al, sp, W, s);
     });
 }
 
-}  // namespace mgemm
-
-using namespace mgemm;
-
-extern "C" {
-
-int32_t gemm_ex(int64_t m, int64_t n, int64_t k, double alpha, const void *A, int64_t lda,
-                const void *B, int64_t ldb, double beta, void *C, int64_t ldc, int32_t dtype,
-                const mgemm_cfg *cfg, void *stream) {
+// gemm_ex: argument checks, configuration choice and launch.
+static int32_t gemm_impl(int64_t m, int64_t n, int64_t k, double alpha, const void *A,
+                         int64_t lda, const void *B, int64_t ldb, double beta, void *C,
+                         int64_t ldc, int32_t dtype, const mgemm_cfg *cfg, void *stream) {
     g_err.clear();
     int32_t rc = check_args(m, n, k, alpha, A, lda, B, ldb, C, ldc, dtype);
     if (rc) return rc;
@@ -333,18 +356,45 @@ int32_t gemm_ex(int64_t m, int64_t n, int64_t k, double alpha, const void *A, in
     if (!cfg) {
         const SplitPlan sp = splitk_plan(a, e, dtype);
         if (sp.S > 1) return run_splitk(e, a, dtype, al, sp, s);
-        // the configuration measured fastest for shapes like this one: always for
-        // rows the three-stage kernels cannot load (which the preference list
-        // favours), else where the list names a two-stage configuration
-        const bool rows16 = rows_whole_loads(a, dtype);
-        if (!rows16 || e->cfg.double_buffer != 2) {
-            const KernelEntry *t = measured_entry(dtype, rows16, m, n, k);
-            if (t) e = t;
+        // a loaded cost model's choice (evaluated on the device once per shape;
+        // calls on a capturing stream use cached choices only)
+        mgemm_cfg mc;
+        const bool may_launch = !capturing(s) && !capturing(g_stream);
+        const KernelEntry *me = nullptr;
+        if (model_choose(dtype, m, n, k, may_launch, &mc) == 0) {
+            int cnt = 0;
+            const KernelEntry *reg = registry(dtype, &cnt);
+            me = find_entry(reg, cnt, mc);
+        }
+        g_err.clear();     // a model that could not be used leaves the built-in choice
+        if (me) {
+            e = me;
+        } else {
+            // the configuration measured fastest for shapes like this one: always for
+            // rows the three-stage kernels cannot load (which the preference list
+            // favours), else where the list names a two-stage configuration
+            const bool rows16 = rows_whole_loads(a, dtype);
+            if (!rows16 || e->cfg.double_buffer != 2) {
+                const KernelEntry *t = measured_entry(dtype, rows16, m, n, k);
+                if (t) e = t;
+            }
         }
     }
     hipError_t he = (al ? e->launch : e->launch_unaligned)(a, s);
     if (he != hipSuccess) return hip_error(he, "gemm launch");
     return 0;
+}
+
+}  // namespace mgemm
+
+using namespace mgemm;
+
+extern "C" {
+
+int32_t gemm_ex(int64_t m, int64_t n, int64_t k, double alpha, const void *A, int64_t lda,
+                const void *B, int64_t ldb, double beta, void *C, int64_t ldc, int32_t dtype,
+                const mgemm_cfg *cfg, void *stream) {
+    return gemm_impl(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, dtype, cfg, stream);
 }
 
 int32_t gemm(int64_t m, int64_t n, int64_t k, double alpha, const void *A, int64_t lda,
@@ -391,6 +441,18 @@ int32_t mgemm_host_free(void *host) {
     if (!host) return 0;
     hipError_t e = hipHostFree(host);
     return e == hipSuccess ? 0 : hip_error(e, "host_free: hipHostFree");
+}
+
+int32_t mgemm_config_flags(int32_t dtype, int32_t i) {
+    if (dtype < MGEMM_F64 || dtype > MGEMM_CRT_INT8) return -1;
+    int cnt = 0;
+    const KernelEntry *reg = registry(dtype, &cnt);
+    if (i < 0 || i >= cnt) return -2;
+    const KernelEntry &e = reg[i];
+    int32_t f = MGEMM_CFG_GEMM;
+    if (e.batched) f |= MGEMM_CFG_BATCHED;
+    if (e.splitk[0] || e.splitk[1]) f |= MGEMM_CFG_SPLITK;
+    return f;
 }
 
 int32_t mgemm_config_get(int32_t dtype, int32_t i, mgemm_cfg *out) {

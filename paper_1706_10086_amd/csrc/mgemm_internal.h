@@ -65,7 +65,11 @@ struct KernelEntry {
                                          // rows; null where the tile has none
 };
 
-// Per-dtype registries, defined in the kernel files.
+// A part of the tuning-grid registry (grid_*.hip, written by gen_grid.py).
+typedef const KernelEntry *(*GridPartFn)(int *count);
+
+// Per-dtype registries, defined in the kernel files: the hand-registered
+// configurations, then the tuning-grid ones.
 const KernelEntry *f64_registry(int *count);
 const KernelEntry *f32_registry(int *count);
 
@@ -122,6 +126,12 @@ hipError_t splitk_reduce(int32_t dtype, const void *W, int S, const GemmArgs &a,
 // `bytes`, ordered on stream s after the workspace's previous user; returns fn's
 // result (or an allocation error).
 int32_t with_workspace(size_t bytes, hipStream_t s, const std::function<int32_t(uint8_t *)> &fn);
+
+// Writes a cost-model file (format in model.hip); 0 or an error code.
+int32_t model_write(const char *path, int I, int H, int O, const int32_t *out_dtype,
+                    const mgemm_cfg *out_cfg, const double *mean, const double *stdv,
+                    const float *params, int64_t P);
+bool cfg_registered(int32_t dtype, const mgemm_cfg &c);
 
 // s_waitcnt immediate for vmcnt(n) (n < 64), no wait on the other counters.
 constexpr int vmcnt_imm(int n) { return (n & 15) | ((n >> 4) << 14) | 0x70 | 0xF00; }

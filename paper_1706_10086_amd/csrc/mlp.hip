@@ -21,7 +21,7 @@ namespace mgemm {
 int32_t set_error(int32_t code, const char *fmt, ...);
 hipStream_t current_stream();
 
-constexpr int MLP_MAX_DIM = 256;
+constexpr int MLP_MAX_DIM = 4096;
 
 // ---------------------------------------------------------------------------
 // Kernels.
@@ -430,6 +430,27 @@ int32_t mlp_predict(void *handle, int64_t rows, const float *X, const float *M, 
     }
     (void)hipFree(y);
     return rc;
+}
+
+int32_t mlp_save(void *handle, const char *path, const int32_t *out_dtype,
+                 const mgemm_cfg *out_cfg, const double *feat_mean, const double *feat_std) {
+    Mlp *p = (Mlp *)handle;
+    if (!p) return set_error(-1, "handle is NULL");
+    if (!path) return set_error(-2, "path is NULL");
+    if (!out_dtype) return set_error(-3, "out_dtype is NULL");
+    if (!out_cfg) return set_error(-4, "out_cfg is NULL");
+    if (!feat_mean) return set_error(-5, "feat_mean is NULL");
+    if (!feat_std) return set_error(-6, "feat_std is NULL");
+    if (p->I != 6)
+        return set_error(MGEMM_ERR_MODEL, "model files hold networks of 6 inputs, not %d", p->I);
+    for (int o = 0; o < p->O; ++o)
+        if (!cfg_registered(out_dtype[o], out_cfg[o]))
+            return set_error(MGEMM_ERR_MODEL, "output %d names a configuration not registered", o);
+    std::vector<float> par((size_t)p->P);
+    const int32_t rc = mlp_get_params(p, par.data());
+    if (rc) return rc;
+    return model_write(path, p->I, p->H, p->O, out_dtype, out_cfg, feat_mean, feat_std, par.data(),
+                       p->P);
 }
 
 int32_t mlp_destroy(void *handle) {

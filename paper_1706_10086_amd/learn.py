@@ -93,6 +93,79 @@ def build_dataset(db, table, shapes_with_dtype) -> Dataset:
     return Dataset(shapes, np.array(X), np.array(T), np.array(M), np.array(TF))
 
 
+# ---------------------------------------------------------------------------
+# The model file (the format mlp_save writes and mgemm_model_load reads; see
+# csrc/model.hip): text, every floating-point value as a C99 hexadecimal float,
+# closed by an FNV-1a checksum of the text before the checksum line.
+# ---------------------------------------------------------------------------
+def c_hex(x: float) -> str:
+    """``x`` as glibc's printf("%a") writes a double (trailing zero digits of the
+    fraction dropped), so that files written here and by the library agree."""
+    mant, exp = float(x).hex().split("p")
+    if "." in mant:
+        mant = mant.rstrip("0").rstrip(".")
+    return mant + "p" + exp
+
+
+def fnv1a64(data: bytes) -> int:
+    h = 0xcbf29ce484222325
+    for b in data:
+        h = ((h ^ b) * 0x100000001b3) & 0xFFFFFFFFFFFFFFFF
+    return h
+
+
+def model_text(table, mean, std, hidden, params) -> str:
+    """The model file for a 6-input network with ``hidden`` units and one output
+    per (dtype, configuration tuple) of ``table``."""
+    params = np.asarray(params, dtype=np.float32)
+    lines = ["mgemm-mlp 1", f"dims {len(mean)} {hidden} {len(table)}"]
+    lines += ["out " + " ".join(str(int(v)) for v in (dt, *c)) for dt, c in table]
+    lines.append("mean " + " ".join(c_hex(v) for v in mean))
+    lines.append("std " + " ".join(c_hex(v) for v in std))
+    lines.append(f"params {params.size}")
+    vals = [c_hex(float(v)) for v in params]
+    lines += [" ".join(vals[i:i + 8]) for i in range(0, len(vals), 8)]
+    body = "\n".join(lines) + "\n"
+    return body + f"checksum {fnv1a64(body.encode()):016x}\n"
+
+
+def parse_model_text(text: str):
+    """(table, mean, std, hidden, params) of a model file; ValueError if the
+    checksum or the syntax is wrong."""
+    cpos = text.rfind("checksum ")
+    if cpos < 0 or (cpos > 0 and text[cpos - 1] != "\n"):
+        raise ValueError("no checksum line")
+    if int(text[cpos + 9:].split()[0], 16) != fnv1a64(text[:cpos].encode()):
+        raise ValueError("checksum mismatch (corrupt file)")
+    tok = text[:cpos].split()
+    if tok[:2] != ["mgemm-mlp", "1"] or tok[2] != "dims":
+        raise ValueError("not an mgemm-mlp version 1 file")
+    I, H, O = (int(t) for t in tok[3:6])
+    pos = 6
+    table = []
+    for _ in range(O):
+        if tok[pos] != "out":
+            raise ValueError("output line missing")
+        v = [int(t) for t in tok[pos + 1:pos + 9]]
+        table.append((v[0], tuple(v[1:])))
+        pos += 9
+    if tok[pos] != "mean":
+        raise ValueError("no mean line")
+    mean = np.array([float.fromhex(t) for t in tok[pos + 1:pos + 1 + I]])
+    pos += 1 + I
+    if tok[pos] != "std":
+        raise ValueError("no std line")
+    std = np.array([float.fromhex(t) for t in tok[pos + 1:pos + 1 + I]])
+    pos += 1 + I
+    if tok[pos] != "params":
+        raise ValueError("no params line")
+    P = int(tok[pos + 1])
+    params = np.array([float.fromhex(t) for t in tok[pos + 2:pos + 2 + P]], dtype=np.float32)
+    if params.size != P or pos + 2 + P != len(tok):
+        raise ValueError("parameter count does not match")
+    return table, mean, std, H, params
+
+
 @dataclass
 class Predictor:
     table: list
@@ -110,6 +183,21 @@ class Predictor:
                            "table_hash": table_hash(self.table), "mean": self.mean.tolist(),
                            "std": self.std.tolist(), "hidden": self.hidden,
                            "params": self.params.tolist(), "history": self.history})
+
+    def save(self, path: str) -> None:
+        """Writes the model file mgemm_model_load reads."""
+        with open(path, "w") as f:
+            f.write(model_text(self.table, self.mean, self.std, self.hidden, self.params))
+
+    @classmethod
+    def load(cls, path: str, check_table=None) -> "Predictor":
+        """Reads a model file (ValueError if corrupt, or, with ``check_table``, if
+        its outputs are not that table)."""
+        with open(path) as f:
+            table, mean, std, hidden, params = parse_model_text(f.read())
+        if check_table is not None and table_hash(check_table) != table_hash(table):
+            raise ValueError("model was trained for a different configuration table")
+        return cls(table, mean, std, params, hidden)
 
     @classmethod
     def from_json(cls, s: str, check_table=None) -> "Predictor":

@@ -3,25 +3,29 @@ shapes, keep the results in an append-only JSONL database, and pick the
 exhaustive best.
 
 The procedure follows the paper's parameter tuning (Sec. 2.3 "Multidimensional
-parameter tuning" and Sec. 3, Tab. 4): a grid of tile parameters is searched,
-each point measured several times and the best kept, at a main size and checked
-at a control size.  Here the grid searched is the library's configuration
-registry (tile M/N/K, waves per work-group, elements per thread, double
-buffering, occupancy), the compiled subset of the valid points of the raw grid
-defined below (``raw_grid``, ``grid_violations``); the measurement is the device time of one gemm_ex call from HIP
-events (warm-up, then ``reps`` timed runs; median and best kept), and a
-configuration whose first timed run is more than ``abandon`` times slower than
-the best so far for that shape is not measured further.
+parameter tuning" and Sec. 3, Tab. 4): a grid of tile parameters is searched and
+each point measured, the best kept.  Here the grid searched is the library's
+configuration registry (tile M/N/K, waves per work-group, elements per thread,
+LDS stages, occupancy): the hand-registered kernels and the compiled subset of
+the valid points of the raw grid defined below (``raw_grid``,
+``grid_violations``).  The measurement is the device time of one gemm_ex call
+from HIP events on the stream it runs on: one timed run, ``reps`` in all unless
+the first is more than ``abandon`` times slower than the shape's best so far
+(then its one time stands, an upper bound of its speed).  Every kernel is run
+once before the sweep, so no timed run loads code.
 
-Database records (one JSON object per line) are keyed by
-(device, build, dtype, m, n, k, cfg); a sweep skips keys already present, so an
-interrupted sweep resumes where it stopped.  Lines that do not parse are skipped
-and counted.
+Database lines are JSON objects of two kinds: a shape record (one line per
+device, dtype and shape: every configuration measured, with its times) written
+by ``sweep``, and the older per-configuration record; ``DB.load`` reads both as
+per-configuration records.  A sweep skips the (device, dtype, shape) triples
+already present, so an interrupted sweep resumes at the shape it stopped in.
+Lines that do not parse are skipped and counted.
 """
 from __future__ import annotations
 
 import hashlib
 import json
+import math
 import os
 import time
 from dataclasses import dataclass
@@ -48,6 +52,23 @@ def key_of(rec: dict) -> tuple:
             tuple(rec["cfg"]))
 
 
+def flops(m, n, k) -> float:
+    return 2.0 * m * n * k
+
+
+def expand_shape_record(r: dict) -> list:
+    """The per-configuration records of one shape record."""
+    out = []
+    for c, t in zip(r["cfgs"], r["ms"]):
+        med = float(np.median(t))
+        out.append({"device": r["device"], "build": r["build"], "dtype": r["dtype"],
+                    "m": r["m"], "n": r["n"], "k": r["k"], "cfg": list(c), "times_ms": t,
+                    "best_ms": min(t), "median_ms": med,
+                    "tflops": flops(r["m"], r["n"], r["k"]) / (med * 1e-3) / 1e12,
+                    "abandoned": len(t) < r.get("reps", len(t))})
+    return out
+
+
 @dataclass
 class DB:
     path: str
@@ -65,8 +86,15 @@ class DB:
                         continue
                     try:
                         r = json.loads(line)
-                        key_of(r)
-                        recs.append(r)
+                        if "cfgs" in r:
+                            if len(r["cfgs"]) != len(r["ms"]) or not all(r["ms"]):
+                                raise ValueError("shape record")
+                            rs = expand_shape_record(r)
+                        else:
+                            rs = [r]
+                        for x in rs:
+                            key_of(x)
+                        recs.extend(rs)
                     except (ValueError, KeyError, TypeError):
                         bad += 1
         return cls(path, recs, bad)
@@ -74,84 +102,174 @@ class DB:
     def keys(self) -> set:
         return {key_of(r) for r in self.records}
 
+    def shapes_done(self, device: str) -> set:
+        """(dtype, m, n, k) measured on ``device``."""
+        return {(r["dtype"], r["m"], r["n"], r["k"]) for r in self.records if r["device"] == device}
+
     def append(self, rec: dict) -> None:
-        self.records.append(rec)
+        """Appends one record (a shape record is kept expanded in memory)."""
+        self.records.extend(expand_shape_record(rec) if "cfgs" in rec else [rec])
         with open(self.path, "a") as f:
-            f.write(json.dumps(rec) + "\n")
+            f.write(json.dumps(rec, separators=(",", ":")) + "\n")
             f.flush()
 
     def for_shape(self, dtype: int, m: int, n: int, k: int) -> list:
         return [r for r in self.records if r["dtype"] == dtype and (r["m"], r["n"], r["k"]) == (m, n, k)]
 
 
-def flops(m, n, k) -> float:
-    return 2.0 * m * n * k
-
-
 # The raw tuning grid (the paper's powers-of-two search of Sec. 2.3 and Tab. 4,
 # widened to the GPU's tile parameters): tile M/N/K, waves per work-group,
-# elements per thread, one or two LDS stages.  Every point is a kernel of its own
-# (tile shapes are template parameters), so the library compiles a subset: the
-# registry.  ``grid_violations`` is the filter that decides which points can be
-# compiled at all; the kernels' static assertions enforce the same rules.
+# elements per thread, one or two LDS stages, and occupancy -- waves per SIMD,
+# the GPU counterpart of the paper's hardware threads per core (Sec. 3, Tab. 4,
+# Fig. 4).  Every point is a kernel of its own (tile shapes are template
+# parameters), so the library compiles a subset: the registry.
+# ``grid_violations`` decides which points can run as specified; it models the
+# kernels' real LDS layout and register use.
 GRID_TILES = (32, 64, 128, 256)
 GRID_WAVES = (1, 2, 4, 8)
 GRID_EPT = (4, 8, 16)
 GRID_DBUF = (0, 1)
-# the registry also uses k-steps of 16 and runs of 2 elements (one 16-byte FP64
-# load): a 256 x 128 FP64 tile with three stages fits the LDS only at bk = 16
+GRID_OCC = (1, 2)
+# the hand-registered kernels also use k-steps of 16 and runs of 2 elements (one
+# 16-byte FP64 load): a 256 x 128 FP64 tile with three stages fits the LDS only
+# at bk = 16
 EXT_BK = (16,)
 EXT_EPT = (2,)
 LDS_BYTES = 160 * 1024          # per compute unit
+SIMDS = 4                       # per compute unit
+LANE_REGS = 512                 # 32-bit registers per lane of one SIMD
 ACC_VGPRS = 256                 # accumulator registers one lane may hold
 MFMA_TILE = 16                  # 16 x 16 output block of the FP64 and FP32 instructions
+BASE_REGS = 24                  # addresses, loop counters and the like
+# Headroom the compiler needs (hipcc for gfx950, checked against its register and
+# scratch report for every grid kernel): tiles whose accumulators fill all 256
+# accumulator registers, or whose estimate at two waves per SIMD passes 240, spill.
+ACC_HEADROOM = 8
+OCC2_HEADROOM = 16
+HOIST_GROUPS = 2                # 8-deep k groups whose fragments are live at once
 
 
-def raw_grid():
-    """All 4^3 * 4 * 3 * 2 = 1536 points (bm, bn, bk, waves, ept, dbuf)."""
-    return [(bm, bn, bk, w, e, d) for bm in GRID_TILES for bn in GRID_TILES for bk in GRID_TILES
-            for w in GRID_WAVES for e in GRID_EPT for d in GRID_DBUF]
+def wave_layout(bm: int, bn: int, waves: int):
+    """(WGM, WGN): the waves' grid over the tile -- whole 16 x 16 instruction
+    blocks per wave, the wave tile closest to square (fewer rows of waves on a
+    tie) -- or None if there is none."""
+    best = None
+    for wgm in GRID_WAVES:
+        if wgm > waves or waves % wgm:
+            continue
+        wgn = waves // wgm
+        if bm % (wgm * MFMA_TILE) or bn % (wgn * MFMA_TILE):
+            continue
+        key = (abs(math.log2((bm // wgm) / (bn // wgn))), wgm)
+        if best is None or key < best[0]:
+            best = (key, (wgm, wgn))
+    return None if best is None else best[1]
+
+
+def lds_bytes(dtype: int, bm: int, bn: int, bk: int, dbuf: int) -> int:
+    """LDS one work-group needs: the two-stage kernel's padded A and B tiles (A
+    rows bk + 2, B rows bn + 8 FP64 / + 16 FP32 elements) per stage (dbuf 0, 1:
+    one, two stages); the three-stage kernel's 16-byte units (A rows one unit
+    longer, B rows 4 FP64 / 2 FP32 units longer) times three (dbuf 2)."""
+    S = 4 if dtype == F32 else 8
+    if dbuf == 2:
+        au = bk * S // 16 + 1
+        bu = bn * S // 16 + (4 if S == 8 else 2)
+        return 3 * 16 * (bm * au + bk * bu)
+    return (bm * (bk + 2) + bk * (bn + (8 if S == 8 else 16))) * S * (1 + dbuf)
+
+
+def reg_estimate(dtype: int, bm: int, bn: int, bk: int, waves: int, ept: int, dbuf: int):
+    """(accumulator registers, other registers) per lane: the C fragments; the
+    staged loads (two-stage kernels: the next k-step's tile in registers), the
+    operand fragments of HOIST_GROUPS k groups (the compiler reads the next group
+    from LDS during the current one), run coordinates and BASE_REGS.  None
+    without a wave layout."""
+    lay = wave_layout(bm, bn, waves)
+    if lay is None:
+        return None
+    s4 = (4 if dtype == F32 else 8) // 4
+    nt = 64 * waves
+    fm, fn = bm // lay[0] // MFMA_TILE, bn // lay[1] // MFMA_TILE
+    acc = bm * bn // nt * s4
+    if dbuf == 2:      # all fragments of a k-step held, one load offset per instruction
+        loads = -(-lds_bytes(dtype, bm, bn, bk, 2) // (3 * 16 * nt))
+        return acc, (bk // 8) * (2 * fm + 2 * fn) * s4 + loads + BASE_REGS
+    stage = (bm * bk + bk * bn) // nt * s4
+    runs = 2 * ((bm * bk) // (ept * nt) + (bk * bn) // (ept * nt))
+    frag = (2 * fm + 2 * fn) * s4 * min(bk // 8, HOIST_GROUPS)
+    return acc, stage + frag + runs + BASE_REGS
 
 
 def grid_violations(dtype: int, bm: int, bn: int, bk: int, waves: int, ept: int,
-                    dbuf: int) -> list:
-    """Names of the rules a configuration breaks (empty: it can be compiled).
+                    dbuf: int, occ: int = 0) -> list:
+    """Names of the rules a configuration breaks (empty: it runs as specified).
 
-    * ``lds``:   the A and B stages, (bm bk + bk bn) S bytes each, fit in the LDS
-                 (``dbuf`` 0, 1, 2: one, two, three stages);
-    * ``acc``:   each lane's share of the bm x bn accumulators fits in 256 VGPRs;
-    * ``mfma``:  the waves split the tile into a WGM x WGN grid of wave tiles that
-                 are whole 16 x 16 instruction blocks;
+    * ``mfma``:  the waves split the tile into whole 16 x 16 instruction blocks
+                 (``wave_layout``);
     * ``loads``: both slabs split into runs of ``ept`` consecutive elements, at
-                 least one per thread, each within one row of the slab.
+                 least one per thread, each within one row of the slab;
+    * ``occ``:   ``occ`` waves per SIMD leave room for at least one work-group
+                 (waves <= 4 occ);
+    * ``lds``:   the LDS of the g work-groups that run ``occ`` waves per SIMD
+                 (g = max(1, 4 occ / waves); one for occ 0) fits in 160 KiB;
+    * ``acc``:   the accumulators fit the 256 accumulator registers of a lane
+                 (with ACC_HEADROOM to spare);
+    * ``regs``:  the registers fit 512 / occ per lane (occ 0 or 1: 256 besides
+                 the accumulators; occ 2: 256 in all, OCC2_HEADROOM to spare).
     """
-    S = 4 if dtype == F32 else 8
     out = []
-    if (bm * bk + bk * bn) * S * (1 + dbuf) > LDS_BYTES:
-        out.append("lds")
-    if bm * bn * (S // 4) > ACC_VGPRS * 64 * waves:
-        out.append("acc")
-    if not any(waves % wgm == 0 and bm % (wgm * MFMA_TILE) == 0
-               and bn % ((waves // wgm) * MFMA_TILE) == 0 for wgm in GRID_WAVES if wgm <= waves):
+    lay = wave_layout(bm, bn, waves)
+    if lay is None:
         out.append("mfma")
     per_pass = 64 * waves * ept
     if (bm * bk) % per_pass or (bk * bn) % per_pass or bm * bk < per_pass \
             or bk * bn < per_pass or ept > bk or ept > bn or ept % 2:
         out.append("loads")
+    groups = 1
+    if occ > 0:
+        groups = SIMDS * occ // waves
+        if groups < 1:
+            out.append("occ")
+            groups = 1
+    if lds_bytes(dtype, bm, bn, bk, dbuf) * groups > LDS_BYTES:
+        out.append("lds")
+    if lay is not None:
+        acc, other = reg_estimate(dtype, bm, bn, bk, waves, ept, dbuf)
+        if acc > ACC_VGPRS - ACC_HEADROOM:
+            out.append("acc")
+        elif (occ <= 1 and other > LANE_REGS - ACC_VGPRS) or \
+                (occ >= 2 and acc + other > LANE_REGS // occ - OCC2_HEADROOM):
+            out.append("regs")
     return out
 
 
+def raw_grid():
+    """All 4^3 * 4 * 3 * 2 * 2 = 3072 points (bm, bn, bk, waves, ept, dbuf, occ)."""
+    return [(bm, bn, bk, w, e, d, o) for bm in GRID_TILES for bn in GRID_TILES
+            for bk in GRID_TILES for w in GRID_WAVES for e in GRID_EPT for d in GRID_DBUF
+            for o in GRID_OCC]
+
+
 def extended_grid():
-    """``raw_grid`` with k-steps of 16 and runs of 2 elements added (2560 points)."""
-    return [(bm, bn, bk, w, e, d) for bm in GRID_TILES for bn in GRID_TILES
+    """``raw_grid`` with k-steps of 16, runs of 2 elements and occupancy 0 (the
+    compiler's choice) added: 4*4*5*4*4*2*3 = 7680 points."""
+    return [(bm, bn, bk, w, e, d, o) for bm in GRID_TILES for bn in GRID_TILES
             for bk in EXT_BK + GRID_TILES for w in GRID_WAVES for e in EXT_EPT + GRID_EPT
-            for d in GRID_DBUF]
+            for d in GRID_DBUF for o in (0,) + GRID_OCC]
 
 
 def valid_grid(dtype: int, extended: bool = False):
     """The points of ``raw_grid`` (or ``extended_grid``) that break no rule."""
     return [p for p in (extended_grid() if extended else raw_grid())
             if not grid_violations(dtype, *p)]
+
+
+def both_occupancy_tiles(dtype: int):
+    """Tiles (bm, bn, bk, waves, ept, dbuf) of the raw grid valid at occupancy 1
+    and at occupancy 2 (the pairs whose comparison measures the occupancy axis)."""
+    v = set(valid_grid(dtype))
+    return sorted({p[:6] for p in v if p[6] == 1} & {p[:6] for p in v if p[6] == 2})
 
 
 class Operands:
@@ -169,11 +287,12 @@ class Operands:
 
 
 def time_config(ops: Operands, dtype: int, cfg, warmup: int = 1, reps: int = 3,
-                abandon_ms: float | None = None) -> list[float]:
-    """Device times (ms) of ``reps`` gemm calls after ``warmup`` untimed ones.
-    Stops after the first timed run if it exceeds ``abandon_ms``."""
+                abandon_ms: float | None = None, stream=None) -> list[float]:
+    """Device times (ms) of ``reps`` gemm calls after ``warmup`` untimed ones, from
+    HIP events on the stream the calls run on.  Stops after the first timed run if
+    it exceeds ``abandon_ms``."""
     import torch
-    stream = torch.cuda.current_stream()
+    stream = stream or torch.cuda.current_stream()
     for _ in range(warmup):
         gemm(ops.A, ops.B, ops.C, 1.0, 0.0, dtype=dtype, cfg=cfg, stream=stream)
     times = []
@@ -188,39 +307,6 @@ def time_config(ops: Operands, dtype: int, cfg, warmup: int = 1, reps: int = 3,
         if abandon_ms is not None and times[-1] > abandon_ms:
             break
     return times
-
-
-def sweep(shapes, dtype: int, db: DB, cfgs=None, reps: int = 3, abandon: float = 2.0,
-          log=None) -> int:
-    """Times every configuration on every shape not yet in ``db``; returns the
-    number of new records."""
-    dev, bid = device_name(), build_id()
-    cfgs = list(cfgs if cfgs is not None else configs(dtype))
-    done = db.keys()
-    new = 0
-    for (m, n, k) in shapes:
-        todo = [c for c in cfgs if (dev, bid, dtype, m, n, k, c.as_tuple()) not in done]
-        if not todo:
-            continue
-        ops = Operands(m, n, k, dtype)
-        best = min((r["best_ms"] for r in db.for_shape(dtype, m, n, k)
-                    if r["device"] == dev and r["build"] == bid), default=None)
-        for c in todo:
-            t = time_config(ops, dtype, c, reps=reps,
-                            abandon_ms=None if best is None else abandon * best)
-            rec = {"device": dev, "build": bid, "dtype": dtype, "m": m, "n": n, "k": k,
-                   "cfg": list(c.as_tuple()), "times_ms": [round(x, 5) for x in t],
-                   "best_ms": min(t), "median_ms": float(np.median(t)),
-                   "tflops": flops(m, n, k) / (float(np.median(t)) * 1e-3) / 1e12,
-                   "abandoned": len(t) < reps, "ts": time.time()}
-            db.append(rec)
-            new += 1
-            best = rec["best_ms"] if best is None else min(best, rec["best_ms"])
-            if log:
-                log(f"  {dtype} {m}x{n}x{k} {c} median {rec['median_ms']:.4f} ms "
-                    f"{rec['tflops']:.2f} TF")
-        del ops
-    return new
 
 
 def exhaustive_best(db: DB, dtype: int, m: int, n: int, k: int):
@@ -307,39 +393,53 @@ class Arena:
         return o
 
 
-def sweep_set(shapes, dtype, db: DB, reps=2, abandon=2.0, log=print, every=25):
-    """Resumable sweep of every registered configuration over ``shapes``."""
+def sweep(shapes, dtype: int, db: DB, cfgs=None, reps: int = 2, abandon: float = 2.0,
+          log=None, every: int = 25, seconds: float | None = None) -> int:
+    """Times every configuration (default: all registered ones of dtype) on every
+    shape not yet in ``db`` for this device, appending one shape record per shape;
+    returns the number of new records.  Configurations are tried in the order of
+    their mean log relative speed over the shapes swept so far (the likely fastest
+    first, so that slow ones are abandoned after one run).  With ``seconds``, no
+    new shape is started after that many seconds."""
+    import torch
+    log = log or (lambda s: None)
     dev, bid = device_name(), build_id()
-    cfgs = list(configs(dtype))
-    done = db.keys()
-    todo = [s for s in shapes
-            if any((dev, bid, dtype, s[0], s[1], s[2], c.as_tuple()) not in done for c in cfgs)]
+    cfgs = list(cfgs if cfgs is not None else configs(dtype))
+    done = db.shapes_done(dev)
+    todo = [tuple(s) for s in shapes if (dtype, *s) not in done]
     if not todo:
         log(f"sweep dtype={dtype}: nothing to do ({len(shapes)} shapes already measured)")
         return 0
-    arena = Arena(todo, dtype)
+    arena = Arena(todo + [(64, 64, 64)], dtype)
+    stream = torch.cuda.current_stream()
+    # load every kernel's code before anything is timed
+    warm = arena.operands(64, 64, 64)
+    for c in cfgs:
+        gemm(warm.A, warm.B, warm.C, 1.0, 0.0, dtype=dtype, cfg=c, stream=stream)
+    torch.cuda.synchronize()
+    score = np.zeros(len(cfgs))
     t0 = time.time()
     new = 0
     for i, (m, n, k) in enumerate(todo):
+        if seconds is not None and time.time() - t0 > seconds:
+            log(f"sweep dtype={dtype}: time budget reached after {i} shapes")
+            break
         ops = arena.operands(m, n, k)
         best = None
-        for c in cfgs:
-            key = (dev, bid, dtype, m, n, k, c.as_tuple())
-            if key in done:
-                continue
-            t = time_config(ops, dtype, c, reps=reps,
-                            abandon_ms=None if best is None else abandon * best)
-            rec = {"device": dev, "build": bid, "dtype": dtype, "m": m, "n": n, "k": k,
-                   "cfg": list(c.as_tuple()), "times_ms": [round(x, 5) for x in t],
-                   "best_ms": min(t), "median_ms": float(np.median(t)),
-                   "tflops": flops(m, n, k) / (float(np.median(t)) * 1e-3) / 1e12,
-                   "abandoned": len(t) < reps, "ts": time.time()}
-            db.append(rec)
-            new += 1
-            best = rec["best_ms"] if best is None else min(best, rec["best_ms"])
+        times = [None] * len(cfgs)
+        for j in np.argsort(-score, kind="stable"):
+            t = time_config(ops, dtype, cfgs[j], warmup=0, reps=reps,
+                            abandon_ms=None if best is None else abandon * best, stream=stream)
+            times[j] = [round(x, 5) for x in t]
+            best = min(t) if best is None else min(best, min(t))
+        db.append({"device": dev, "build": bid, "dtype": dtype, "m": m, "n": n, "k": k,
+                   "reps": reps, "cfgs": [list(c.as_tuple()) for c in cfgs], "ms": times,
+                   "ts": round(time.time(), 1)})
+        new += 1
+        med = np.array([float(np.median(t)) for t in times])
+        score += np.log(med.min() / med)
         if (i + 1) % every == 0 or i + 1 == len(todo):
-            log(f"sweep dtype={dtype}: {i + 1}/{len(todo)} shapes, {new} records, "
-                f"{time.time() - t0:.0f} s")
+            log(f"sweep dtype={dtype}: {i + 1}/{len(todo)} shapes, {time.time() - t0:.0f} s")
     return new
 
 
@@ -354,7 +454,8 @@ def batch_rules(dtype: int) -> dict:
     out: in a plan they run their two-stage fallback, registered on its own), and
     mixtures of the 64 x 64 four-wave tile with the smallest tile for thin
     problems (min(m, n) <= T) or a 128 x 128 tile for large ones (min(m, n) >= T)."""
-    cs = [c.as_tuple() for c in configs(dtype) if c.double_buffer < 2]
+    from . import CFG_BATCHED
+    cs = [c.as_tuple() for c in configs(dtype, CFG_BATCHED) if c.double_buffer < 2]
     rules = {f"all {c}": (lambda m, n, k, c=c: c) for c in cs}
     mid = next((c for c in cs if c[:4] == (64, 64, 16, 4)), None)
     small = min(cs, key=lambda c: (c[0] * c[1], c[2]))
@@ -413,18 +514,18 @@ def main(argv=None):
     ap.add_argument("--db", required=True)
     ap.add_argument("--count", type=int, default=None)
     ap.add_argument("--reps", type=int, default=2)
+    ap.add_argument("--seconds", type=float, default=None,
+                    help="start no new shape after this many seconds")
     a = ap.parse_args(argv)
     dt = F64 if a.dtype == "f64" else F32
     db = DB.load(a.db)
     if db.bad_lines:
         print(f"tune: skipped {db.bad_lines} unreadable database lines", flush=True)
     shapes = shape_set(a.set, a.count)
-    n = sweep_set(shapes, dt, db, reps=a.reps, log=lambda s: print(s, flush=True))
-    print(f"tune: {n} new records in {a.db}", flush=True)
+    n = sweep(shapes, dt, db, reps=a.reps, log=lambda s: print(s, flush=True), seconds=a.seconds)
+    print(f"tune: {n} new shape records in {a.db}", flush=True)
 
 
-if __name__ == "__main__":
-    main()
 
 
 # ---------------------------------------------------------------------------
@@ -467,3 +568,7 @@ def load_compact(path: str) -> DB:
                          "cfg": list(c), "tflops": v, "best_ms": flops(m, n, k) / (v * 1e9),
                          "median_ms": flops(m, n, k) / (v * 1e9)})
     return DB(path, recs, 0)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,62 @@
+"""The autotuner's sweep on the GPU, into a temporary database: every registered
+configuration is timed on a few shapes (one shape record each); a second run of
+the same sweep adds nothing (it resumes); the exhaustive best is the fastest
+configuration measured; re-timing that configuration reproduces its time within
+10 %; and it computes the product within the oracle's error bound."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1706_10086_amd as mg  # noqa: E402
+from paper_1706_10086_amd import tune  # noqa: E402
+
+SHAPES = [(640, 896, 512), (1000, 333, 777), (1536, 1536, 1024)]
+
+
+@pytest.mark.parametrize("dt", [mg.F64, mg.F32])
+def test_sweep_resumes_and_finds_a_reproducible_best(dt, tmp_path):
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import oracle
+    import synth
+    path = str(tmp_path / "db.jsonl")
+    db = tune.DB.load(path)
+    log = lambda s: print(s, flush=True)  # noqa: E731
+    cfgs = mg.configs(dt)
+    assert tune.sweep(SHAPES, dt, db, reps=3, log=log) == len(SHAPES)
+    db2 = tune.DB.load(path)
+    assert db2.bad_lines == 0 and len(db2.records) == len(SHAPES) * len(cfgs)
+    assert tune.sweep(SHAPES, dt, db2, reps=3, log=log) == 0
+    dev = torch.device("cuda:0")
+    tdt = torch.float64 if dt == mg.F64 else torch.float32
+    for i, (m, n, k) in enumerate(SHAPES):
+        recs = db2.for_shape(dt, m, n, k)
+        assert {tuple(r["cfg"]) for r in recs} == {c.as_tuple() for c in cfgs}
+        cfg, tf = tune.exhaustive_best(db2, dt, m, n, k)
+        assert tf == max(r["tflops"] for r in recs)
+        assert tune.regret(db2, dt, m, n, k, cfg) == 0.0
+        win = next(r for r in recs if tuple(r["cfg"]) == cfg)
+        assert not win["abandoned"]
+        ops = tune.Operands(m, n, k, dt)
+        again = tune.time_config(ops, dt, mg.Cfg(*cfg), warmup=1, reps=5)
+        med = float(np.median(again))
+        print(f"sweep dt={dt} {(m, n, k)} best {cfg}: {win['median_ms']:.4f} ms, "
+              f"re-timed {med:.4f} ms", flush=True)
+        assert abs(med - win["median_ms"]) <= 0.10 * win["median_ms"]
+        # the winner's product against the oracle
+        A = synth.uniform_pm1((m, k), 9500 + i)
+        B = synth.uniform_pm1((k, n), 9600 + i)
+        if dt == mg.F32:
+            A, B = (x.astype(np.float32).astype(np.float64) for x in (A, B))
+        C = torch.zeros((m, n), device=dev, dtype=tdt)
+        mg.gemm(torch.from_numpy(A).to(dev, tdt), torch.from_numpy(B).to(dev, tdt), C, 1.0, 0.0,
+                cfg=mg.Cfg(*cfg))
+        torch.cuda.synchronize()
+        rows = np.array([0, m // 2, m - 1])
+        ref = oracle.gemm_dot2(1.0, A[rows], B, nthreads=oracle.num_procs())
+        got = C[torch.from_numpy(rows).to(dev)].cpu().double().numpy()
+        u = 2.0 ** -24 if dt == mg.F32 else 2.0 ** -53
+        bound = (k + 2) * u / (1 - (k + 2) * u) * (np.abs(A[rows]) @ np.abs(B))
+        assert np.all(np.abs(got - ref) <= bound)

@@ -41,6 +41,27 @@ def test_db_resumes_and_skips_corrupt_lines(tmp_path):
     assert ("dev", "b", 0, 64, 64, 64, (1, 2, 3, 4, 5, 6, 8)) in db2.keys()
 
 
+def test_shape_records_expand_and_resume(tmp_path):
+    """A sweep writes one line per shape (every configuration with its times); the
+    database reads it as per-configuration records, and knows which shapes a
+    device has done."""
+    p = tmp_path / "db.jsonl"
+    db = tune.DB.load(str(p))
+    db.append({"device": "gpu0", "build": "b", "dtype": 1, "m": 100, "n": 200, "k": 300,
+               "reps": 2, "cfgs": [[1, 2, 3, 4, 5, 6, 7], [7, 6, 5, 4, 3, 2, 1]],
+               "ms": [[0.5, 0.7], [2.0]], "ts": 1.0})
+    with open(p, "a") as f:
+        f.write('{"device": "gpu0", "cfgs": [[1]], "ms": [[]], "dtype": 1}\n')   # no times
+    db2 = tune.DB.load(str(p))
+    assert db2.bad_lines == 1 and len(db2.records) == 2
+    r0, r1 = sorted(db2.records, key=lambda r: r["cfg"])
+    assert r0["median_ms"] == 0.6 and r0["best_ms"] == 0.5 and not r0["abandoned"]
+    assert r1["abandoned"] and r1["tflops"] == pytest.approx(2 * 100 * 200 * 300 / 2e-3 / 1e12)
+    assert db2.shapes_done("gpu0") == {(1, 100, 200, 300)}
+    assert db2.shapes_done("other") == set()
+    assert tune.exhaustive_best(db2, 1, 100, 200, 300)[0] == (1, 2, 3, 4, 5, 6, 7)
+
+
 def test_exhaustive_best_and_regret():
     db = tune.DB("x", [rec(0, 8, 8, 8, (1,), 10.0), rec(0, 8, 8, 8, (2,), 40.0),
                        rec(0, 8, 8, 8, (3,), 30.0), rec(1, 8, 8, 8, (1,), 99.0)])
@@ -117,31 +138,54 @@ def test_shipped_database_covers_the_registry():
 
 def test_raw_grid_and_validity_rules():
     g = tune.raw_grid()
-    assert len(g) == 1536 and len(set(g)) == 1536
-    f64, f32 = tune.valid_grid(0), tune.valid_grid(1)
+    assert len(g) == 3072 and len(set(g)) == 3072
+    f64, f32 = set(tune.valid_grid(0)), set(tune.valid_grid(1))
     # FP32 halves the LDS and accumulator footprint: every valid FP64 point is a
     # valid FP32 point
-    assert set(f64) < set(f32)
-    # each rule on a point that breaks only it
-    assert tune.grid_violations(0, 256, 256, 64, 4, 4, 1) == ["lds", "acc"]
-    assert tune.grid_violations(1, 256, 256, 64, 4, 4, 1) == ["lds"]
-    assert tune.grid_violations(0, 256, 256, 16, 1, 4, 0) == ["acc"]
-    assert tune.grid_violations(0, 32, 32, 32, 8, 4, 0) == ["mfma", "loads"]
-    assert tune.grid_violations(0, 64, 32, 32, 2, 16, 1) == ["loads"]
-    assert tune.grid_violations(0, 64, 64, 32, 4, 4, 1) == []
+    assert f64 < f32
+    # each rule on a point that breaks it
+    assert tune.grid_violations(0, 32, 32, 32, 8, 4, 0, 2) == ["mfma", "loads"]
+    assert tune.grid_violations(0, 64, 32, 32, 2, 16, 1, 1) == ["loads"]
+    assert tune.grid_violations(0, 64, 64, 32, 8, 4, 0, 1) == ["occ"]
+    assert tune.grid_violations(0, 256, 256, 64, 4, 4, 1, 1) == ["lds", "acc"]
+    assert tune.grid_violations(1, 128, 128, 128, 4, 4, 1, 1) == ["lds"]
+    assert tune.grid_violations(0, 256, 256, 32, 8, 4, 0, 2) == ["acc"]
+    # the same tile at one and at two waves per SIMD: two work-groups must fit the
+    # LDS, and all registers must fit 256 per lane
+    assert tune.grid_violations(0, 64, 64, 32, 4, 4, 1, 1) == []
+    assert tune.grid_violations(0, 64, 64, 32, 4, 4, 1, 2) == []
+    assert tune.grid_violations(0, 128, 128, 64, 4, 4, 0, 1) == []
+    assert tune.grid_violations(0, 128, 128, 32, 4, 4, 0, 2) == ["regs"]
+    assert tune.grid_violations(0, 128, 128, 32, 4, 4, 1, 2) == ["lds", "regs"]
+    # occupancy 2 with 8 waves: one work-group of two waves per SIMD
+    assert tune.grid_violations(0, 128, 128, 32, 8, 4, 0, 2) == []
+
+
+def test_wave_layout_and_footprints():
+    assert tune.wave_layout(256, 128, 8) == (4, 2)
+    assert tune.wave_layout(128, 64, 4) == (2, 2)
+    assert tune.wave_layout(32, 32, 4) == (2, 2)
+    assert tune.wave_layout(32, 32, 8) is None
+    # LDS of the kernels' padded stages (two-stage) and 16-byte units (three-stage)
+    assert tune.lds_bytes(0, 128, 128, 16, 1) == 2 * (128 * 18 + 16 * 136) * 8
+    assert tune.lds_bytes(1, 128, 128, 32, 1) == 2 * (128 * 34 + 32 * 144) * 4
+    assert tune.lds_bytes(0, 256, 128, 16, 2) == 3 * 16 * (256 * 9 + 16 * 68)
+    acc, other = tune.reg_estimate(0, 128, 128, 16, 4, 2, 1)
+    assert acc == 128 and other > 0
 
 
 def test_registry_lies_in_the_valid_space():
-    """Every compiled configuration is a valid point of the extended grid (k-steps
-    of 16 and 2-element runs added); three-stage entries count three stages."""
-    assert len(tune.extended_grid()) == 2560
+    """Every compiled configuration runs as specified: it breaks no rule, and the
+    two-stage ones are points of the extended grid (k-steps of 16, 2-element runs
+    and occupancy 0 added)."""
+    assert len(tune.extended_grid()) == 7680
     for dt in (mg.F64, mg.F32):
         ext = set(tune.valid_grid(dt, extended=True))
         for c in mg.configs(dt):
-            p = (c.bm, c.bn, c.bk, c.waves, c.elems_per_thread, min(c.double_buffer, 1))
-            assert p in ext, c.as_tuple()
             assert tune.grid_violations(dt, c.bm, c.bn, c.bk, c.waves, c.elems_per_thread,
-                                        c.double_buffer) == [], c.as_tuple()
+                                        c.double_buffer, c.occupancy) == [], c.as_tuple()
+            if c.double_buffer < 2:
+                assert c.as_tuple() in ext, c.as_tuple()
 
 
 def test_batch_rules_map_every_shape_to_a_registered_configuration():
@@ -150,9 +194,12 @@ def test_batch_rules_map_every_shape_to_a_registered_configuration():
     for dt in (mg.F64, mg.F32):
         reg = {c.as_tuple() for c in mg.configs(dt)}
         rules = tune.batch_rules(dt)
-        # one rule per registered two-stage configuration, plus the mixtures
+        # one rule per registered two-stage configuration that batched plans take,
+        # plus the mixtures
         singles = [r for r in rules if r.startswith("all ")]
-        assert len(singles) == sum(1 for c in mg.configs(dt) if c.double_buffer < 2)
+        assert len(singles) == sum(1 for c in mg.configs(dt, mg.CFG_BATCHED)
+                                   if c.double_buffer < 2)
+        reg = {c.as_tuple() for c in mg.configs(dt, mg.CFG_BATCHED)}
         assert len(rules) > len(singles)
         for name, rule in rules.items():
             got = {rule(m, n, k) for m, n, k in shapes}
