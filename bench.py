@@ -146,62 +146,57 @@ def cpu_baseline(n, A, B, C, budget_s):
 
 
 def leg_split(mg, torch, dev, n=8192, with_small=True):
+    """The emulated FP64 dtypes and plain FP64 on the wide-range stress inputs at
+    N = 8192 (256 rows spread evenly over the matrix checked) and N / 2 (every
+    element checked): time, FP64-equivalent TFLOP/s, and the normwise error
+    against the double-double (Dot2) oracle and against the plain FP64 oracle."""
     import oracle
     import synth
-    log(f"bench: split leg, N={n} wide-range inputs")
-    sa, sb, _ = synth.seeds_for(2, int(np.log2(n)))
-    A = synth.wide_range((n, n), sa)
-    B = synth.wide_range((n, n), sb)
-    tA, tB = torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev)
-    tC = torch.zeros((n, n), device=dev, dtype=torch.float64)
-    stream = torch.cuda.current_stream()
-    rows = np.array([0, 1, 1000, 2222, 4096, 5000, 7777, n - 1])
-    log("bench: split leg, Dot2 oracle on sampled rows")
-    ref = oracle.gemm_dot2(1.0, A[rows], B, nthreads=oracle.num_procs())
-    out = {"n": n, "inputs": "u*2^e, u uniform[-1,1], e uniform integer in [-20,20]",
-           "error": f"normwise vs double-double oracle on {len(rows)} sampled rows"}
-    for name, dt in (("f64", mg.F64), ("bf16", mg.SPLIT_BF16), ("fp8", mg.SPLIT_FP8),
-                     ("int8", mg.SPLIT_INT8), ("crt_int8", mg.CRT_INT8)):
-        ts = timed(lambda: mg.gemm(tA, tB, tC, 1.0, 0.0, dtype=dt, stream=stream), stream, 5)
-        got = tC[torch.from_numpy(rows).to(dev)].cpu().numpy()
-        err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
-        ms = float(np.mean(ts))
-        out[name] = {"ms": round(ms, 4), "tflops_fp64_equiv": round(2.0 * n ** 3 / ms / 1e9, 3),
-                     "pct_fp64_peak": round(100 * 2.0 * n ** 3 / ms / 1e9 / PEAK_F64_TFLOPS, 2),
-                     "rel_err": err}
-        log(f"  {name}: {ms:.3f} ms, err {err:.2e}")
-    out["bf16"]["mfma_util"] = round(21 * 2.0 * n ** 3 / (out["bf16"]["ms"] * 1e9) / PEAK_BF16_TFLOPS, 4)
-    out["fp8"]["mfma_util"] = round(66 * 2.0 * n ** 3 / (out["fp8"]["ms"] * 1e9) / PEAK_FP8_TFLOPS, 4)
-    out["int8"]["mfma_util"] = round(36 * 2.0 * n ** 3 / (out["int8"]["ms"] * 1e9) / PEAK_INT8_TOPS, 4)
-    # 16 int8 GEMMs of the zero-padded operands (one per modulus)
-    npad = -(-n // 256) * 256
-    kpad = -(-n // 64) * 64
-    out["crt_int8"]["mfma_util"] = round(16 * 2.0 * npad * npad * kpad /
-                                         (out["crt_int8"]["ms"] * 1e9) / PEAK_INT8_TOPS, 4)
-    del tA, tB, tC
-    torch.cuda.empty_cache()
-    if not with_small:
-        return out
-    # the smaller split size, same recipe
-    m = n // 2
-    sa, sb, _ = synth.seeds_for(2, int(np.log2(m)))
-    A = synth.wide_range((m, m), sa)
-    B = synth.wide_range((m, m), sb)
-    tA, tB = torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev)
-    tC = torch.zeros((m, m), device=dev, dtype=torch.float64)
-    rows = np.array([0, 1, 1000, 2222, 3000, m - 1])
-    ref = oracle.gemm_dot2(1.0, A[rows], B, nthreads=oracle.num_procs())
-    small = {"n": m}
-    for name, dt in (("f64", mg.F64), ("bf16", mg.SPLIT_BF16), ("fp8", mg.SPLIT_FP8),
-                     ("int8", mg.SPLIT_INT8), ("crt_int8", mg.CRT_INT8)):
-        ts = timed(lambda: mg.gemm(tA, tB, tC, 1.0, 0.0, dtype=dt, stream=stream), stream, 5)
-        got = tC[torch.from_numpy(rows).to(dev)].cpu().numpy()
-        ms = float(np.mean(ts))
-        small[name] = {"ms": round(ms, 4), "tflops_fp64_equiv": round(2.0 * m ** 3 / ms / 1e9, 3),
-                       "rel_err": float(np.linalg.norm(got - ref) / np.linalg.norm(ref))}
-        log(f"  n={m} {name}: {ms:.3f} ms, err {small[name]['rel_err']:.2e}")
-    out[f"n{m}"] = small
-    del tA, tB, tC
+    out = {"inputs": "u*2^e, u uniform[-1,1], e uniform integer in [-20,20]; alpha 1, beta 0",
+           "error": "normwise, against the double-double (Dot2) oracle (rel_err) and the plain "
+                    "FP64 oracle (rel_err_vs_f64_oracle)"}
+    sizes = [(n, 256)] + ([(n // 2, None)] if with_small else [])
+    for size, count in sizes:
+        log(f"bench: split leg, N={size} wide-range inputs")
+        sa, sb, _ = synth.seeds_for(2, int(np.log2(size)))
+        A = synth.wide_range((size, size), sa)
+        B = synth.wide_range((size, size), sb)
+        rows = np.arange(size) if count is None else np.linspace(0, size - 1, count).astype(np.int64)
+        log(f"bench: split leg, Dot2 and FP64 oracles on {len(rows)} rows")
+        ref = oracle.gemm_dot2(1.0, A[rows], B, nthreads=oracle.num_procs())
+        ref64 = oracle.gemm_f64(1.0, A[rows], B, nthreads=oracle.num_procs())
+        tA, tB = torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev)
+        del A, B
+        tC = torch.zeros((size, size), device=dev, dtype=torch.float64)
+        trows = torch.from_numpy(rows).to(dev)
+        stream = torch.cuda.current_stream()
+        res = {"n": size, "rows_checked": len(rows),
+               "f64_oracle_vs_dot2": float(np.linalg.norm(ref64 - ref) / np.linalg.norm(ref))}
+        for name, dt in (("f64", mg.F64), ("bf16", mg.SPLIT_BF16), ("fp8", mg.SPLIT_FP8),
+                         ("int8", mg.SPLIT_INT8), ("crt_int8", mg.CRT_INT8)):
+            ts = timed(lambda: mg.gemm(tA, tB, tC, 1.0, 0.0, dtype=dt, stream=stream), stream, 5)
+            got = tC[trows].cpu().numpy()
+            ms = float(np.mean(ts))
+            res[name] = {"ms": round(ms, 4), "tflops_fp64_equiv": round(2.0 * size ** 3 / ms / 1e9, 3),
+                         "pct_fp64_peak": round(100 * 2.0 * size ** 3 / ms / 1e9 / PEAK_F64_TFLOPS, 2),
+                         "rel_err": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
+                         "rel_err_vs_f64_oracle": float(np.linalg.norm(got - ref64) / np.linalg.norm(ref64))}
+            log(f"  n={size} {name}: {ms:.3f} ms, err {res[name]['rel_err']:.2e} (Dot2), "
+                f"{res[name]['rel_err_vs_f64_oracle']:.2e} (FP64 oracle)")
+        res["bf16"]["mfma_util"] = round(21 * 2.0 * size ** 3 / (res["bf16"]["ms"] * 1e9) / PEAK_BF16_TFLOPS, 4)
+        res["fp8"]["mfma_util"] = round(66 * 2.0 * size ** 3 / (res["fp8"]["ms"] * 1e9) / PEAK_FP8_TFLOPS, 4)
+        res["int8"]["mfma_util"] = round(36 * 2.0 * size ** 3 / (res["int8"]["ms"] * 1e9) / PEAK_INT8_TOPS, 4)
+        # 16 int8 GEMMs of the zero-padded operands (one per modulus)
+        npad = -(-size // 256) * 256
+        kpad = -(-size // 64) * 64
+        res["crt_int8"]["mfma_util"] = round(16 * 2.0 * npad * npad * kpad /
+                                             (res["crt_int8"]["ms"] * 1e9) / PEAK_INT8_TOPS, 4)
+        if size == n:
+            out.update(res)
+        else:
+            out[f"n{size}"] = res
+        del tA, tB, tC
+        torch.cuda.empty_cache()
     return out
 
 
@@ -423,10 +418,11 @@ def leg_memory(mg, torch, dev, sizes=(1024, 2048, 4096, 8192)):
     return out
 
 
-def live_recheck(mg, pred, table, count=12):
+def live_recheck(mg, pred, table, count=8):
     """Re-times held-out FP64 shapes now: TFLOP/s of the predicted configuration,
     and of the library's built-in choice (no configuration named), over the best of
-    all registered configurations, measured in this run."""
+    all registered configurations, measured in this run (each configuration once
+    after one untimed run, a second time unless more than twice the best so far)."""
     import torch
     from paper_1706_10086_amd import learn, tune
     shapes = [s for s in tune.shape_set("heldout") if 2.0 * s[0] * s[1] * s[2] < 2e11][:count]
@@ -435,8 +431,11 @@ def live_recheck(mg, pred, table, count=12):
     for (m, n, k), c in zip(shapes, choice):
         ops = tune.Operands(m, n, k, mg.F64)
         tf = {}
+        best = None
         for cfg in mg.configs(mg.F64):
-            t = tune.time_config(ops, mg.F64, cfg, warmup=1, reps=3)
+            t = tune.time_config(ops, mg.F64, cfg, warmup=1, reps=2,
+                                 abandon_ms=None if best is None else 2.0 * best)
+            best = min(t) if best is None else min(best, min(t))
             tf[cfg.as_tuple()] = tune.flops(m, n, k) / (min(t) * 1e9)
         t = tune.time_config(ops, mg.F64, None, warmup=1, reps=3)
         fr.append(tf[table[c][1]] / max(tf.values()))
@@ -444,6 +443,67 @@ def live_recheck(mg, pred, table, count=12):
         del ops
     torch.cuda.empty_cache()
     return learn.summarize(np.array(fr)), learn.summarize(np.array(fb))
+
+
+def occupancy_gain(db, shapes, dtype):
+    """The occupancy axis (waves per SIMD, the paper's hardware threads per core)
+    on the held-out shapes of ``dtype``, from the database: per shape, the best
+    occupancy-2 configuration over the best occupancy-1 configuration among the
+    tiles compiled at both occupancies (geometric mean over shapes, and per tile
+    family); and the exhaustive best with against without occupancy-2 points."""
+    by = {}
+    for r in db.records:
+        if r["dtype"] == dtype:
+            by.setdefault((r["m"], r["n"], r["k"]), {})[tuple(r["cfg"])] = r["tflops"]
+    cfgs = {c for row in by.values() for c in row}
+    fam1 = {c[:6] for c in cfgs if c[6] == 1}
+    both = {f for f in fam1 if f + (2,) in cfgs}
+    best_ratio, with_without, per_tile = [], [], {f: [] for f in both}
+    for sh in shapes:
+        row = by.get(tuple(sh))
+        if not row:
+            continue
+        o1 = [row[f + (1,)] for f in both if f + (1,) in row]
+        o2 = [row[f + (2,)] for f in both if f + (2,) in row]
+        if o1 and o2:
+            best_ratio.append(max(o2) / max(o1))
+        without = [v for c, v in row.items() if c[6] != 2]
+        if without:
+            with_without.append(max(row.values()) / max(without))
+        for f in both:
+            if f + (1,) in row and f + (2,) in row:
+                per_tile[f].append(row[f + (2,)] / row[f + (1,)])
+    gm = lambda x: float(np.exp(np.mean(np.log(x)))) if len(x) else None  # noqa: E731
+    tiles = {f: gm(v) for f, v in per_tile.items() if v}
+    return {"tile_families_at_both": len(both), "shapes": len(best_ratio),
+            "best_occ2_over_best_occ1": gm(best_ratio),
+            "share_shapes_occ2_faster": float(np.mean(np.array(best_ratio) > 1.0)) if best_ratio else None,
+            "exhaustive_with_over_without_occ2": gm(with_without),
+            "per_tile_family_geomean_min": min(tiles.values()) if tiles else None,
+            "per_tile_family_geomean_max": max(tiles.values()) if tiles else None,
+            "tile_families_occ2_faster": sum(1 for v in tiles.values() if v > 1.0)}
+
+
+def model_latency(mg, pred, shapes, tmpdir):
+    """Inference latency of the learned model through the C ABI: a model file
+    written from ``pred``, loaded with mgemm_model_load; mgemm_model_predict per
+    shape on first sight (one forward pass on the GPU) and again (cached)."""
+    path = os.path.join(tmpdir, "bench_model.txt")
+    pred.save(path)
+    mg.model_load(path)
+    try:
+        t = time.perf_counter()
+        for (dt, m, n, k) in shapes:
+            mg.model_predict(m, n, k, dt)
+        first = (time.perf_counter() - t) / len(shapes)
+        t = time.perf_counter()
+        for (dt, m, n, k) in shapes:
+            mg.model_predict(m, n, k, dt)
+        cached = (time.perf_counter() - t) / len(shapes)
+    finally:
+        mg.model_load(None)
+    return {"shapes": len(shapes), "first_call_us": round(1e6 * first, 1),
+            "cached_call_us": round(1e6 * cached, 2)}
 
 
 def leg_tuner(mg):
@@ -460,23 +520,39 @@ def leg_tuner(mg):
     dho = learn.build_dataset(db, table, ho)
     if not dtr.shapes or not dho.shapes:
         return {"status": "tuner database does not match the configuration registry"}
+    steps = 6000
     t0 = time.time()
-    pred = learn.train(dtr, table, steps=6000, lr=2e-3)
+    pred = learn.train(dtr, table, steps=steps, lr=2e-3)
     t_train = time.time() - t0
+    t0 = time.time()
     choice = learn.predict(pred, dho.shapes)
+    t_pred = time.time() - t0
     base = learn.single_best_baseline(dtr, table)
     mlp = learn.summarize(learn.achieved(dho, choice))
     single = learn.summarize(learn.achieved(dho, [base[s[0]] for s in dho.shapes]))
     top3 = learn.summarize(learn.top_k_fallback(dho, pred, 3))
+    import tempfile
+    with tempfile.TemporaryDirectory() as td:
+        lat = model_latency(mg, pred, dho.shapes[:50], td)
+    occ = {name: occupancy_gain(db, tune.shape_set("heldout"), dt)
+           for name, dt in (("f64", mg.F64), ("f32", mg.F32))}
+    per = {}
+    for name, dt in (("f64", mg.F64), ("f32", mg.F32)):
+        rows = [i for i, s in enumerate(dho.shapes) if s[0] == dt]
+        per[name] = learn.summarize(learn.achieved(dho, [choice[i] for i in rows])) if rows else None
     log("bench: tuner leg, live re-timing of held-out shapes")
     live, builtin = live_recheck(mg, pred, table)
-    return {"database": "paper_1706_10086_amd/data/tune_db.json.gz (MI355X sweep: 3000 train + "
-                        "500 held-out + 800 aligned shapes, m,n,k log-uniform in [64,16384], "
-                        "FP64 and FP32, every registered configuration)",
+    return {"database": "paper_1706_10086_amd/data/tune_db.json.gz (MI355X sweep, m,n,k log-uniform "
+                        "in [64,16384], FP64 and FP32, every registered configuration)",
+            "configurations": {"f64": len(mg.configs(mg.F64)), "f32": len(mg.configs(mg.F32))},
             "train_rows": len(dtr.shapes), "heldout_rows": len(dho.shapes),
-            "train_s": round(t_train, 2), "mlp": mlp, "single_best_config": single,
+            "train_s": round(t_train, 2), "adam_steps": steps,
+            "ms_per_adam_step": round(1e3 * t_train / steps, 4),
+            "predict_heldout_ms": round(1e3 * t_pred, 2), "model_predict_c_abi": lat,
+            "mlp": mlp, "mlp_per_dtype": per, "single_best_config": single,
             "mlp_top3_measured": top3, "regret_geomean": round(1.0 - mlp["geomean"], 4),
             "gain_over_single": round(mlp["geomean"] / single["geomean"], 4),
+            "occupancy_axis": occ,
             "live_recheck_f64": live, "builtin_choice_live_f64": builtin}
 
 

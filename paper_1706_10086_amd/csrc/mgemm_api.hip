@@ -32,11 +32,11 @@ int32_t set_error(int32_t code, const char *fmt, ...) {
     return code;
 }
 
-static int32_t hip_error(hipError_t e, const char *where) {
+int32_t hip_error(hipError_t e, const char *where) {
     return set_error(MGEMM_ERR_HIP, "%s: %s", where, hipGetErrorString(e));
 }
 
-static size_t elem_size(int32_t dtype) {
+size_t elem_size(int32_t dtype) {
     return dtype == MGEMM_F32 ? 4 : 8;
 }
 
@@ -87,7 +87,7 @@ __global__ void scale_c_kernel(T *C, int64_t m, int64_t n, int64_t ldc, T beta) 
     }
 }
 
-static int32_t scale_c(int32_t dtype, int64_t m, int64_t n, double beta, void *C, int64_t ldc,
+int32_t scale_c(int32_t dtype, int64_t m, int64_t n, double beta, void *C, int64_t ldc,
                        hipStream_t s) {
     if (beta == 1.0) return 0;
     int64_t total = m * n;
@@ -275,12 +275,6 @@ static int compute_units() {
     return cached[dev];
 }
 
-struct SplitPlan {
-    int S = 1;              // number of k ranges (1: no split)
-    int64_t kc = 0;         // k per range
-    bool pipe = false;      // three-stage 128 x 128 tile
-};
-
 // S ranges wanted -> the ranges actually cut (kc rounded up to SPLITK_MIN_K)
 static void cut_k(int64_t k, int64_t want, SplitPlan &sp) {
     want = std::min<int64_t>(std::min<int64_t>(want, k / SPLITK_MIN_K), SPLITK_MAX);
@@ -315,7 +309,7 @@ static SplitPlan splitk_plan(const GemmArgs &a, const KernelEntry *e, int32_t dt
 
 // The partial products and their reduction, in W (the caller's buffer of at least
 // S*m*n elements).
-static int32_t launch_splitk_into(const KernelEntry *e, const GemmArgs &a, int32_t dtype,
+int32_t launch_splitk_into(const KernelEntry *e, const GemmArgs &a, int32_t dtype,
                                   bool al, const SplitPlan &sp, uint8_t *W, hipStream_t s) {
     hipError_t he = sp.pipe ? launch_pipe_splitk(a, dtype, sp.S, sp.kc, W, s)
                             : e->splitk[al ? 0 : 1](a, sp.S, sp.kc, W, s);
@@ -330,6 +324,47 @@ static int32_t run_splitk(const KernelEntry *e, const GemmArgs &a, int32_t dtype
     return with_workspace((size_t)sp.S * a.m * a.n * es, s, [&](uint8_t *W) -> int32_t {
         return launch_splitk_into(e, a, dtype, al, sp, W, s);
     });
+}
+
+// What gemm_ex runs for one FP64 or FP32 product (CallPlan, mgemm_internal.h).
+// A loaded cost model is evaluated on the device only when model_may_launch
+// (else only its cached choices are used).
+int32_t plan_call(const GemmArgs &a, int32_t dtype, const mgemm_cfg *cfg,
+                         bool model_may_launch, CallPlan &cp) {
+    int32_t err = 0;
+    const KernelEntry *e = choose_entry(dtype, a.m, a.n, cfg, &err);
+    if (!e) return err;
+    cp.al = rows_aligned(a.A, a.lda, a.B, a.ldb, dtype);
+    if (!cfg) {
+        cp.sp = splitk_plan(a, e, dtype);
+        if (cp.sp.S > 1) {
+            cp.e = e;
+            return 0;
+        }
+        // a loaded cost model's choice (evaluated on the device once per shape)
+        mgemm_cfg mc;
+        const KernelEntry *me = nullptr;
+        if (model_choose(dtype, a.m, a.n, a.k, model_may_launch, &mc) == 0) {
+            int cnt = 0;
+            const KernelEntry *reg = registry(dtype, &cnt);
+            me = find_entry(reg, cnt, mc);
+        }
+        g_err.clear();     // a model that could not be used leaves the built-in choice
+        if (me) {
+            e = me;
+        } else {
+            // the configuration measured fastest for shapes like this one: always for
+            // rows the three-stage kernels cannot load (which the preference list
+            // favours), else where the list names a two-stage configuration
+            const bool rows16 = rows_whole_loads(a, dtype);
+            if (!rows16 || e->cfg.double_buffer != 2) {
+                const KernelEntry *t = measured_entry(dtype, rows16, a.m, a.n, a.k);
+                if (t) e = t;
+            }
+        }
+    }
+    cp.e = e;
+    return 0;
 }
 
 // gemm_ex: argument checks, configuration choice and launch.
@@ -349,38 +384,12 @@ static int32_t gemm_impl(int64_t m, int64_t n, int64_t k, double alpha, const vo
     }
     GemmArgs a{m, n, k, alpha, beta, A, lda, B, ldb, C, ldc};
     if (dtype >= MGEMM_SPLIT_BF16) return split_gemm(a, dtype, s);
-    int32_t err = 0;
-    const KernelEntry *e = choose_entry(dtype, m, n, cfg, &err);
-    if (!e) return err;
-    const bool al = rows_aligned(A, lda, B, ldb, dtype);
-    if (!cfg) {
-        const SplitPlan sp = splitk_plan(a, e, dtype);
-        if (sp.S > 1) return run_splitk(e, a, dtype, al, sp, s);
-        // a loaded cost model's choice (evaluated on the device once per shape;
-        // calls on a capturing stream use cached choices only)
-        mgemm_cfg mc;
-        const bool may_launch = !capturing(s) && !capturing(g_stream);
-        const KernelEntry *me = nullptr;
-        if (model_choose(dtype, m, n, k, may_launch, &mc) == 0) {
-            int cnt = 0;
-            const KernelEntry *reg = registry(dtype, &cnt);
-            me = find_entry(reg, cnt, mc);
-        }
-        g_err.clear();     // a model that could not be used leaves the built-in choice
-        if (me) {
-            e = me;
-        } else {
-            // the configuration measured fastest for shapes like this one: always for
-            // rows the three-stage kernels cannot load (which the preference list
-            // favours), else where the list names a two-stage configuration
-            const bool rows16 = rows_whole_loads(a, dtype);
-            if (!rows16 || e->cfg.double_buffer != 2) {
-                const KernelEntry *t = measured_entry(dtype, rows16, m, n, k);
-                if (t) e = t;
-            }
-        }
-    }
-    hipError_t he = (al ? e->launch : e->launch_unaligned)(a, s);
+    // calls on a capturing stream use cached model choices only
+    CallPlan cp;
+    rc = plan_call(a, dtype, cfg, !capturing(s) && !capturing(g_stream), cp);
+    if (rc) return rc;
+    if (cp.sp.S > 1) return run_splitk(cp.e, a, dtype, cp.al, cp.sp, s);
+    hipError_t he = (cp.al ? cp.e->launch : cp.e->launch_unaligned)(a, s);
     if (he != hipSuccess) return hip_error(he, "gemm launch");
     return 0;
 }

@@ -127,6 +127,41 @@ hipError_t splitk_reduce(int32_t dtype, const void *W, int S, const GemmArgs &a,
 // result (or an allocation error).
 int32_t with_workspace(size_t bytes, hipStream_t s, const std::function<int32_t(uint8_t *)> &fn);
 
+// The split of k of the built-in choice (split-k): S ranges of kc values each;
+// S = 1 means no split.
+struct SplitPlan {
+    int S = 1;              // number of k ranges (1: no split)
+    int64_t kc = 0;         // k per range
+    bool pipe = false;      // three-stage 128 x 128 tile
+};
+
+// What gemm_ex runs for one FP64 or FP32 product: the kernel entry, whether A
+// and B rows take vector loads (al), and for the built-in choice the split of k.
+struct CallPlan {
+    const KernelEntry *e = nullptr;
+    bool al = false;
+    SplitPlan sp;
+};
+
+// gemm_ex's choice for a checked, non-trivial FP64/FP32 product (cfg: the
+// caller's configuration or NULL); a loaded cost model is evaluated on the
+// device only when model_may_launch, else only its cached choices count.
+int32_t plan_call(const GemmArgs &a, int32_t dtype, const mgemm_cfg *cfg, bool model_may_launch,
+                  CallPlan &cp);
+// The S partial products of a split plan into W (at least S*m*n elements) and
+// their reduction into C, on stream s.
+int32_t launch_splitk_into(const KernelEntry *e, const GemmArgs &a, int32_t dtype, bool al,
+                           const SplitPlan &sp, uint8_t *W, hipStream_t s);
+// C = beta*C for dtype MGEMM_F64 or MGEMM_F32 (beta == 0 writes zeros).
+int32_t scale_c(int32_t dtype, int64_t m, int64_t n, double beta, void *C, int64_t ldc,
+                hipStream_t s);
+int32_t check_args(int64_t m, int64_t n, int64_t k, double alpha, const void *A, int64_t lda,
+                   const void *B, int64_t ldb, const void *C, int64_t ldc, int32_t dtype);
+int32_t hip_error(hipError_t e, const char *where);
+int32_t set_error(int32_t code, const char *fmt, ...);
+size_t elem_size(int32_t dtype);
+hipStream_t current_stream();
+
 // Writes a cost-model file (format in model.hip); 0 or an error code.
 int32_t model_write(const char *path, int I, int H, int O, const int32_t *out_dtype,
                     const mgemm_cfg *out_cfg, const double *mean, const double *stdv,

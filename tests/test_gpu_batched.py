@@ -103,7 +103,7 @@ def test_graph_replays_identical(dev):
 def test_plan_with_explicit_configs(dev):
     say("batched plan explicit configs")
     As, Bs, Cs, _ = make_batch(dev, 40, 16, 200, 31, torch.float64)
-    cfgs = mg.configs(mg.F64)
+    cfgs = mg.configs(mg.F64, mg.CFG_BATCHED)
     pick = [cfgs[i % len(cfgs)] for i in range(len(As))]
     Cref = [c.clone() for c in Cs]
     plan = mg.BatchedPlan(As, Bs, Cs, 1.0, 1.0, cfgs=pick)
@@ -213,7 +213,7 @@ def test_plan_without_tile_map(dev, orc):
     search over one list of tile numbers: still bitwise equal to per-problem gemm_ex
     with the same configurations, and sampled rows of the tall problem match the
     oracle."""
-    cfgs = mg.configs(mg.F64)
+    cfgs = mg.configs(mg.F64, mg.CFG_BATCHED)
     c32 = [c for c in cfgs if c.bm == 32][0]
     c64 = [c for c in cfgs if (c.bm, c.bn, c.bk) == (64, 64, 16)][0]
     m_tall = (1 << 25) + 5

@@ -38,7 +38,8 @@ def to_dev(x, dev):
     return torch.from_numpy(np.ascontiguousarray(x)).to(dev)
 
 
-@pytest.mark.parametrize("I,H,O,B", [(6, 5, 4, 7), (6, 64, 19, 300), (6, 64, 19, 3000)])
+@pytest.mark.parametrize("I,H,O,B", [(6, 5, 4, 7), (6, 64, 19, 300), (6, 64, 19, 3000), (6, 8, 70, 130),
+                                     (6, 64, 250, 6000), (3, 100, 129, 1000)])
 def test_loss_and_gradient_match_oracle(dev, I, H, O, B):
     say(f"mlp grad I={I} H={H} O={O} B={B}")
     theta, X, T, M = problem(I, H, O, B, 10 + B)
