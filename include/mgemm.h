@@ -157,6 +157,24 @@ MGEMM_API int32_t gemm_ex(int64_t m, int64_t n, int64_t k, double alpha,
                 double beta, void *C, int64_t ldc, int32_t dtype,
                 const mgemm_cfg *cfg, void *stream);
 
+/* gemm_ex without device allocation, for callers that cannot allocate: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, checks, choice and results as gemm_ex (bitwise, for the same
+ * configuration and split of k) for dtype MGEMM_F64 and MGEMM_F32; any other
+ * dtype returns -12 (the emulated dtypes need the library workspace).  A loaded
+ * cost model (mgemm_model_load) is used only for shapes whose choice it has
+ * already cached (it is never evaluated here); otherwise the built-in choice
+ * applies.  The split-k partial products go to a 64 MiB device array of the
+ * library (one per GPU, kept until the process ends), which every split-k plan
+ * of a 256-CU GPU fits; a plan that would need more returns MGEMM_ERR_NOMEM
+ * with the sizes in mgemm_last_error().  Every call on one GPU shares that
+ * array: calls that overlap on one GPU (different streams, several threads)
+ * race; order them on one stream.  Asynchronous on the stream like gemm_ex. */
+MGEMM_API int32_t gemm_ex_noalloc(int64_t m, int64_t n, int64_t k, double alpha,
+                                  const void *A, int64_t lda, const void *B, int64_t ldb,
+                                  double beta, void *C, int64_t ldc, int32_t dtype,
+                                  const mgemm_cfg *cfg, void *stream);
+
 /*
  * Batched GEMM: count independent problems C_i = alpha_i A_i B_i + beta_i C_i
  * (Eq. 1 per problem), dtype MGEMM_F64 or MGEMM_F32 for plans (any dtype for

@@ -33,7 +33,7 @@ EXPORTED = [
     "mgemm_config_get", "mgemm_release_workspace", "mgemm_probe_mfma", "mgemm_probe_mfma_raw",
     "gemm_batched", "gemm_batched_plan_create", "gemm_batched_plan_execute",
     "gemm_batched_plan_destroy", "gemm_batched_plan_info", "mgemm_host_alloc", "mgemm_host_free",
-    "mgemm_config_flags",
+    "mgemm_config_flags", "gemm_ex_noalloc",
 ]
 CFG_GEMM, CFG_BATCHED, CFG_SPLITK = 1, 2, 4
 
@@ -81,6 +81,8 @@ def lib():
     L.gemm_ex.argtypes = [i64, i64, i64, d, p, i64, p, i64, d, p, i64, i32,
                           ctypes.POINTER(Cfg), p]
     L.gemm_ex.restype = i32
+    L.gemm_ex_noalloc.argtypes = L.gemm_ex.argtypes
+    L.gemm_ex_noalloc.restype = i32
     L.mgemm_set_stream.argtypes = [p]
     L.mgemm_set_stream.restype = i32
     L.mgemm_last_error.argtypes = []
@@ -142,6 +144,13 @@ def gemm_raw(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, dtype) -> int:
 def gemm_ex_raw(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, dtype, cfg=None, stream=None) -> int:
     return lib().gemm_ex(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, dtype, _cfg_ptr(cfg),
                          stream)
+
+
+def gemm_ex_noalloc_raw(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, dtype, cfg=None,
+                        stream=None) -> int:
+    """The C ``gemm_ex_noalloc`` (no device allocation); returns the code."""
+    return lib().gemm_ex_noalloc(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, dtype,
+                                 _cfg_ptr(cfg), stream)
 
 
 class HostBuffer:

@@ -66,6 +66,22 @@ def test_invalid_arguments(L, args, code):
     assert mg.last_error() != ""
 
 
+@pytest.mark.parametrize("args,code", [
+    ((-1, 4, 4, 1.0, P, 4, P, 4, 0.0, P * 2, 4, 0), -1),
+    ((4, 4, 8, 1.0, P, 7, P, 4, 0.0, P * 2, 4, 1), -6),
+    ((4, 4, 4, 1.0, P, 4, P * 4, 4, 0.0, P + 64, 4, 0), -10),
+    # the emulated dtypes need the library workspace
+    ((4, 4, 4, 1.0, P, 4, P * 4, 4, 0.0, P * 2, 4, 2), -12),
+    ((4, 4, 4, 1.0, P, 4, P * 4, 4, 0.0, P * 2, 4, 5), -12),
+    ((4, 4, 4, 1.0, P, 4, P * 4, 4, 0.0, P * 2, 4, 9), -12),
+])
+def test_noalloc_invalid_arguments(L, args, code):
+    assert mg.gemm_ex_noalloc_raw(*args) == code
+    assert mg.last_error() != ""
+    # empty problems return before any device work
+    assert mg.gemm_ex_noalloc_raw(0, 4, 4, 1.0, 0, 4, 0, 4, 0.0, 0, 4, 0) == 0
+
+
 def test_empty_problems_return_without_device_work(L):
     # m == 0 or n == 0: nothing to do, NULL pointers allowed
     assert mg.gemm_raw(0, 4, 4, 1.0, 0, 4, 0, 4, 0.0, 0, 4, 0) == 0
