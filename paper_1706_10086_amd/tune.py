@@ -516,16 +516,21 @@ def main(argv=None):
     ap.add_argument("--reps", type=int, default=2)
     ap.add_argument("--seconds", type=float, default=None,
                     help="start no new shape after this many seconds")
+    ap.add_argument("--skip", default=None,
+                    help="text file of 'dtype m n k' lines: shapes measured elsewhere (for "
+                         "sweeps split over several databases)")
     a = ap.parse_args(argv)
     dt = F64 if a.dtype == "f64" else F32
     db = DB.load(a.db)
     if db.bad_lines:
         print(f"tune: skipped {db.bad_lines} unreadable database lines", flush=True)
     shapes = shape_set(a.set, a.count)
+    if a.skip:
+        with open(a.skip) as f:
+            done = {tuple(int(x) for x in line.split()) for line in f if line.strip()}
+        shapes = [s for s in shapes if (dt, *s) not in done]
     n = sweep(shapes, dt, db, reps=a.reps, log=lambda s: print(s, flush=True), seconds=a.seconds)
     print(f"tune: {n} new shape records in {a.db}", flush=True)
-
-
 
 
 # ---------------------------------------------------------------------------
