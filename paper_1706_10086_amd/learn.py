@@ -9,9 +9,11 @@ exhaustive sweep remains the fallback and the measure of the prediction's regret
 
 * features  x = [log2 m, log2 n, log2 k, onehot(F64, F32, split-BF16)], scaled
             by the training set's mean and standard deviation;
-* targets   r_c = TFLOP/s(c) / max_c' TFLOP/s(c') for every configuration c of
-            the shape's dtype (a masked multi-output regression; configurations
-            of other dtypes are masked out);
+* targets   r_c^p with r_c = TFLOP/s(c) / max_c' TFLOP/s(c') for every
+            configuration c of the shape's dtype (a masked multi-output
+            regression; configurations of other dtypes are masked out); the power
+            p (TARGET_POWER) leaves the arg-max unchanged and spends the fit on the
+            configurations near the best, which are the ones the choice turns on;
 * model     the library's MLP (6 -> 64 -> 64 -> V, FP32), trained by its own HIP
             kernels with Adam on the masked mean square error;
 * choice    masked arg-max of the prediction;
@@ -211,8 +213,14 @@ class Predictor:
                    d["hidden"], d.get("history", []))
 
 
-def train(ds: Dataset, table, hidden=64, steps=4000, lr=2e-3, seed=5, log=None) -> Predictor:
-    """Fits the MLP on the GPU with the library's kernels (full-batch Adam)."""
+TARGET_POWER = 4.0
+
+
+def train(ds: Dataset, table, hidden=64, steps=4000, lr=2e-3, seed=5, log=None,
+          power: float = TARGET_POWER, final_steps: int = 0, final_lr: float | None = None
+          ) -> Predictor:
+    """Fits the MLP on the GPU with the library's kernels (full-batch Adam):
+    ``steps`` steps at ``lr``, then ``final_steps`` more at ``final_lr``."""
     import torch
     mean = ds.X.mean(axis=0)
     std = ds.X.std(axis=0)
@@ -222,18 +230,20 @@ def train(ds: Dataset, table, hidden=64, steps=4000, lr=2e-3, seed=5, log=None) 
     net = MLP(I, hidden, O, init)
     dev = torch.device("cuda")
     Xs = torch.from_numpy(((ds.X - mean) / std).astype(np.float32)).to(dev)
-    net.set_data(Xs, torch.from_numpy(ds.T.astype(np.float32)).to(dev),
+    net.set_data(Xs, torch.from_numpy((ds.T ** power).astype(np.float32)).to(dev),
                  torch.from_numpy(ds.M.astype(np.float32)).to(dev))
     hist = []
     done = 0
     chunk = 500
-    while done < steps:
-        s = min(chunk, steps - done)
-        loss = net.train(s, lr=lr)
-        done += s
-        hist.append((done, float(loss)))
-        if log:
-            log(f"  mlp step {done}: loss {loss:.5f}")
+    for n_steps, rate in ((steps, lr), (final_steps, final_lr)):
+        end = done + n_steps
+        while done < end:
+            s = min(chunk, end - done)
+            loss = net.train(s, lr=rate)
+            done += s
+            hist.append((done, float(loss)))
+            if log:
+                log(f"  mlp step {done}: loss {loss:.5f}")
     params = net.get_params()
     net.destroy()
     return Predictor(table, mean, std, params, hidden, hist)

@@ -65,8 +65,21 @@ def expand_shape_record(r: dict) -> list:
                     "m": r["m"], "n": r["n"], "k": r["k"], "cfg": list(c), "times_ms": t,
                     "best_ms": min(t), "median_ms": med,
                     "tflops": flops(r["m"], r["n"], r["k"]) / (med * 1e-3) / 1e12,
-                    "abandoned": len(t) < r.get("reps", len(t))})
+                    "abandoned": len(t) < r.get("reps", len(t)),
+                    "refined": bool(r.get("refine", False))})
     return out
+
+
+def prefer_refined(records: list) -> list:
+    """Drops the sweep's measurement of a (device, dtype, shape, configuration)
+    that a refinement pass measured again (``refine``): the refined median of
+    more runs replaces it."""
+    ref = {(r["device"], r["dtype"], r["m"], r["n"], r["k"], tuple(r["cfg"]))
+           for r in records if r.get("refined")}
+    if not ref:
+        return records
+    return [r for r in records if r.get("refined") or
+            (r["device"], r["dtype"], r["m"], r["n"], r["k"], tuple(r["cfg"])) not in ref]
 
 
 @dataclass
@@ -97,18 +110,30 @@ class DB:
                         recs.extend(rs)
                     except (ValueError, KeyError, TypeError):
                         bad += 1
-        return cls(path, recs, bad)
+        return cls(path, prefer_refined(recs), bad)
 
     def keys(self) -> set:
         return {key_of(r) for r in self.records}
 
     def shapes_done(self, device: str) -> set:
-        """(dtype, m, n, k) measured on ``device``."""
-        return {(r["dtype"], r["m"], r["n"], r["k"]) for r in self.records if r["device"] == device}
+        """(dtype, m, n, k) measured on ``device`` by a sweep."""
+        return {(r["dtype"], r["m"], r["n"], r["k"]) for r in self.records
+                if r["device"] == device and not r.get("refined")}
+
+    def shapes_refined(self, device: str) -> set:
+        """(dtype, m, n, k) measured on ``device`` by a refinement pass."""
+        return {(r["dtype"], r["m"], r["n"], r["k"]) for r in self.records
+                if r["device"] == device and r.get("refined")}
 
     def append(self, rec: dict) -> None:
         """Appends one record (a shape record is kept expanded in memory)."""
         self.records.extend(expand_shape_record(rec) if "cfgs" in rec else [rec])
+        if rec.get("refine"):
+            self.records = prefer_refined(self.records)
+        self.write_line(rec)
+
+    def write_line(self, rec: dict) -> None:
+        """Appends one record to the file only (``load`` reads it back)."""
         with open(self.path, "a") as f:
             f.write(json.dumps(rec, separators=(",", ":")) + "\n")
             f.flush()
@@ -443,6 +468,66 @@ def sweep(shapes, dtype: int, db: DB, cfgs=None, reps: int = 2, abandon: float =
     return new
 
 
+def refine(shapes, dtype: int, db: DB, top: int = 8, min_ms: float = 2.0, max_reps: int = 40,
+           log=None, every: int = 100, seconds: float | None = None) -> int:
+    """Measures again, with more runs, the ``top`` configurations the sweep found
+    fastest on each shape of ``shapes`` in ``db`` (this device): each is run once
+    untimed, then timed ``reps`` times, ``reps`` = enough runs for ``min_ms`` of
+    kernel time (at least 5, at most ``max_reps``), and its median kept.  Near-ties
+    between configurations (about half the shapes have a runner-up within 2 % of
+    the best, and one run of a short kernel varies by several per cent) are thus
+    decided on a median of many runs; the refined measurements replace the sweep's
+    for those configurations (``prefer_refined``) when the database is loaded
+    again.  Appends one record per shape to the database's file; returns the
+    number of new records.  Shapes already refined are skipped."""
+    import torch
+    log = log or (lambda s: None)
+    dev, bid = device_name(), build_id()
+    valid = {c.as_tuple(): c for c in configs(dtype)}
+    done = db.shapes_refined(dev)
+    todo = [tuple(s) for s in shapes if (dtype, *s) not in done]
+    if not todo:
+        return 0
+    arena = Arena(todo + [(64, 64, 64)], dtype)
+    stream = torch.cuda.current_stream()
+    warm = arena.operands(64, 64, 64)
+    for c in valid.values():
+        gemm(warm.A, warm.B, warm.C, 1.0, 0.0, dtype=dtype, cfg=c, stream=stream)
+    torch.cuda.synchronize()
+    want = set(todo)
+    by_shape = {}
+    for r in db.records:
+        if r["dtype"] == dtype and r["device"] == dev and (r["m"], r["n"], r["k"]) in want \
+                and tuple(r["cfg"]) in valid:
+            by_shape.setdefault((r["m"], r["n"], r["k"]), []).append(r)
+    t0 = time.time()
+    new = 0
+    for i, (m, n, k) in enumerate(todo):
+        if seconds is not None and time.time() - t0 > seconds:
+            log(f"refine dtype={dtype}: time budget reached after {i} shapes")
+            break
+        rs = by_shape.get((m, n, k), [])
+        if not rs:
+            continue
+        rs.sort(key=lambda r: r["median_ms"])
+        pick = [tuple(r["cfg"]) for r in rs[:top]]
+        ops = arena.operands(m, n, k)
+        reps = int(min(max_reps, max(5, math.ceil(min_ms / max(rs[0]["median_ms"], 1e-3)))))
+        times = []
+        for c in pick:
+            t = time_config(ops, dtype, valid[c], warmup=1, reps=reps, stream=stream)
+            times.append([round(x, 5) for x in t])
+        # written to the file only: the refined medians take effect when the
+        # database is loaded again
+        db.write_line({"device": dev, "build": bid, "dtype": dtype, "m": m, "n": n, "k": k,
+                       "reps": reps, "refine": True, "cfgs": [list(c) for c in pick], "ms": times,
+                       "ts": round(time.time(), 1)})
+        new += 1
+        if (i + 1) % every == 0 or i + 1 == len(todo):
+            log(f"refine dtype={dtype}: {i + 1}/{len(todo)} shapes, {time.time() - t0:.0f} s")
+    return new
+
+
 # ---------------------------------------------------------------------------
 # Batched plans: which tile configuration each problem of a batch runs with.
 # The problems of a plan share the GPU, so a choice is scored by timing the
@@ -516,6 +601,12 @@ def main(argv=None):
     ap.add_argument("--reps", type=int, default=2)
     ap.add_argument("--seconds", type=float, default=None,
                     help="start no new shape after this many seconds")
+    ap.add_argument("--refine", type=int, default=0,
+                    help="instead of sweeping: re-time the N fastest configurations of every "
+                         "shape of the set already in --db (and --from databases)")
+    ap.add_argument("--from", dest="sources", action="append", default=[],
+                    help="(with --refine) further databases holding the sweep's records "
+                         "(JSONL, or the compact .json.gz form)")
     ap.add_argument("--skip", default=None,
                     help="text file of 'dtype m n k' lines: shapes measured elsewhere (for "
                          "sweeps split over several databases)")
@@ -525,6 +616,14 @@ def main(argv=None):
     if db.bad_lines:
         print(f"tune: skipped {db.bad_lines} unreadable database lines", flush=True)
     shapes = shape_set(a.set, a.count)
+    if a.refine:
+        for src in a.sources:
+            extra = load_compact(src) if src.endswith(".gz") else DB.load(src)
+            db.records = prefer_refined(db.records + extra.records)
+        n = refine(shapes, dt, db, top=a.refine, log=lambda s: print(s, flush=True),
+                   seconds=a.seconds)
+        print(f"tune: {n} new refinement records in {a.db}", flush=True)
+        return
     if a.skip:
         with open(a.skip) as f:
             done = {tuple(int(x) for x in line.split()) for line in f if line.strip()}

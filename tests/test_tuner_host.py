@@ -219,3 +219,31 @@ def test_aligned_shape_set():
     assert tune.shape_set("aligned")[:7] == al[:7]
     with pytest.raises(ValueError):
         tune.shape_set("other")
+
+
+def test_refinement_records_replace_the_sweeps_measurements(tmp_path):
+    """A refinement pass re-times a shape's fastest configurations with more runs:
+    its medians replace the sweep's for those configurations (the others keep the
+    sweep's), the shape still counts as swept, and the exhaustive best is taken
+    over the merged measurements."""
+    p = tmp_path / "db.jsonl"
+    db = tune.DB.load(str(p))
+    fl = tune.flops(100, 200, 300)
+    sweep = {"device": "d", "build": "b", "dtype": 0, "m": 100, "n": 200, "k": 300, "reps": 2,
+             "cfgs": [[1, 1, 1, 1, 1, 1, 1], [2, 2, 2, 2, 2, 2, 2], [3, 3, 3, 3, 3, 3, 3]],
+             "ms": [[1.0, 1.0], [0.9, 1.1], [2.0]]}
+    db.append(sweep)
+    assert tune.exhaustive_best(db, 0, 100, 200, 300)[0] == (1, 1, 1, 1, 1, 1, 1)
+    refined = dict(sweep, reps=5, refine=True, cfgs=sweep["cfgs"][:2],
+                   ms=[[1.2] * 5, [0.95, 0.96, 0.97, 0.98, 0.99]])
+    db.append(refined)
+    for d in (db, tune.DB.load(str(p))):
+        rs = d.for_shape(0, 100, 200, 300)
+        assert len(rs) == 3
+        by = {tuple(r["cfg"]): r for r in rs}
+        assert by[(1, 1, 1, 1, 1, 1, 1)]["median_ms"] == 1.2 and by[(1, 1, 1, 1, 1, 1, 1)]["refined"]
+        assert by[(3, 3, 3, 3, 3, 3, 3)]["median_ms"] == 2.0 and not by[(3, 3, 3, 3, 3, 3, 3)]["refined"]
+        cfg, tf = tune.exhaustive_best(d, 0, 100, 200, 300)
+        assert cfg == (2, 2, 2, 2, 2, 2, 2) and tf == pytest.approx(fl / (0.97e-3) / 1e12)
+        assert d.shapes_done("d") == {(0, 100, 200, 300)}
+        assert d.shapes_refined("d") == {(0, 100, 200, 300)}
