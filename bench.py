@@ -514,15 +514,13 @@ def leg_tuner(mg):
     log("bench: tuner leg, training the MLP on the tuner database")
     db = tune.load_compact(path)
     table = learn.config_table()
-    tr = [(dt, *s) for dt in (mg.F64, mg.F32) for s in tune.shape_set("train")]
-    ho = [(dt, *s) for dt in (mg.F64, mg.F32) for s in tune.shape_set("heldout")]
-    dtr = learn.build_dataset(db, table, tr)
-    dho = learn.build_dataset(db, table, ho)
+    dtr, dho = learn.datasets(db, table)
     if not dtr.shapes or not dho.shapes:
         return {"status": "tuner database does not match the configuration registry"}
-    steps = 6000
+    settings = learn.TRAIN_SETTINGS
+    steps = settings["steps"] + settings.get("final_steps", 0)
     t0 = time.time()
-    pred = learn.train(dtr, table, steps=steps, lr=2e-3)
+    pred = learn.train(dtr, table, **settings)
     t_train = time.time() - t0
     t0 = time.time()
     choice = learn.predict(pred, dho.shapes)
@@ -539,13 +537,15 @@ def leg_tuner(mg):
     per = {}
     for name, dt in (("f64", mg.F64), ("f32", mg.F32)):
         rows = [i for i, s in enumerate(dho.shapes) if s[0] == dt]
-        per[name] = learn.summarize(learn.achieved(dho, [choice[i] for i in rows])) if rows else None
+        per[name] = learn.summarize(learn.achieved(dho, choice)[rows]) if rows else None
     log("bench: tuner leg, live re-timing of held-out shapes")
     live, builtin = live_recheck(mg, pred, table)
     return {"database": "paper_1706_10086_amd/data/tune_db.json.gz (MI355X sweep, m,n,k log-uniform "
                         "in [64,16384], FP64 and FP32, every registered configuration)",
             "configurations": {"f64": len(mg.configs(mg.F64)), "f32": len(mg.configs(mg.F32))},
             "train_rows": len(dtr.shapes), "heldout_rows": len(dho.shapes),
+            "training": dict(settings, target_power=learn.TARGET_POWER,
+                             sets=list(learn.TRAIN_SETS)),
             "train_s": round(t_train, 2), "adam_steps": steps,
             "ms_per_adam_step": round(1e3 * t_train / steps, 4),
             "predict_heldout_ms": round(1e3 * t_pred, 2), "model_predict_c_abi": lat,

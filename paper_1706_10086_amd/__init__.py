@@ -74,6 +74,12 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise MgemmNotBuilt(f"{LIB_PATH} is missing: run `python -m paper_1706_10086_amd.build`")
+    # torch (device memory and streams for the binding) is loaded first: with the
+    # library's HIP runtime loaded before torch's, torch finds no GPU
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(LIB_PATH)
     i64, i32, d, p = ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_void_p
     L.gemm.argtypes = [i64, i64, i64, d, p, i64, p, i64, d, p, i64, i32]

@@ -7,7 +7,9 @@ GEMM's configuration is chosen per call:
 
 1. ``database`` -- the shape was timed by the tuner: its exhaustive best;
 2. ``model``    -- otherwise the MLP cost model predicts one (evaluated by the
-                   library's HIP kernels);
+                   library's HIP kernels); with ``measure_top = k`` the k best
+                   predicted configurations are run once each on operands of
+                   the shape and the fastest is kept (``measured``);
 3. ``default``  -- no model (or no GPU to evaluate it): the library's built-in
                    preference list (``cfg = None``).
 
@@ -23,8 +25,9 @@ DATA = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data")
 
 class ConfigChooser:
     def __init__(self, db_path: str | None = os.path.join(DATA, "tune_db.json.gz"),
-                 model_path: str | None = os.path.join(DATA, "model.json")):
+                 model_path: str | None = os.path.join(DATA, "model.mlp"), measure_top: int = 0):
         from . import tune
+        self.measure_top = measure_top
         self._best = {}
         if db_path and os.path.exists(db_path):
             db = tune.load_compact(db_path)
@@ -45,8 +48,7 @@ class ConfigChooser:
     def _model(self):
         if self._pred is None and self._model_path and os.path.exists(self._model_path):
             from . import learn
-            with open(self._model_path) as f:
-                self._pred = learn.Predictor.from_json(f.read(), check_table=learn.config_table())
+            self._pred = learn.Predictor.load(self._model_path, check_table=learn.config_table())
         return self._pred
 
     def choose(self, m: int, n: int, k: int, dtype: int = F64):
@@ -63,12 +65,29 @@ class ConfigChooser:
                 import torch
                 if pred is not None and torch.cuda.is_available():
                     from . import learn
-                    slot = learn.predict(pred, [(dtype, m, n, k)])[0]
-                    out = (Cfg(*pred.table[slot][1]), "model")
+                    if self.measure_top > 1:
+                        out = (self._measured(pred, dtype, m, n, k), "measured")
+                    else:
+                        slot = learn.predict(pred, [(dtype, m, n, k)])[0]
+                        out = (Cfg(*pred.table[slot][1]), "model")
             except (ImportError, ValueError, OSError):
                 out = (None, "default")
         self._cache[key] = out
         return out
+
+    def _measured(self, pred, dtype, m, n, k):
+        """The fastest of the model's measure_top best predictions, each timed
+        once (after one untimed run) on operands of the shape drawn for it."""
+        from . import learn, tune
+        slots = learn.ranked(pred, [(dtype, m, n, k)], self.measure_top)[0]
+        ops = tune.Operands(m, n, k, dtype)
+        best, best_t = None, None
+        for j in slots:
+            cfg = Cfg(*pred.table[j][1])
+            t = min(tune.time_config(ops, dtype, cfg, warmup=1, reps=1))
+            if best_t is None or t < best_t:
+                best, best_t = cfg, t
+        return best
 
 
 _default = None

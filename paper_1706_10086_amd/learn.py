@@ -277,6 +277,24 @@ def predict(pred: Predictor, shapes_with_dtype) -> list:
     return [int(i) for i in idx]
 
 
+def ranked(pred: Predictor, shapes_with_dtype, k: int = 3) -> list:
+    """The ``k`` slots with the highest predictions of each shape's dtype, best
+    first (the network evaluated by the library's GPU kernels)."""
+    import torch
+    X = np.array([raw_features(m, n, kk, dt) for (dt, m, n, kk) in shapes_with_dtype])
+    I, O = X.shape[1], len(pred.table)
+    net = MLP(I, pred.hidden, O, pred.params)
+    try:
+        Y = net.forward(torch.from_numpy(pred.scaled(X).astype(np.float32)).cuda()).cpu().numpy()
+    finally:
+        net.destroy()
+    out = []
+    for (dt, _, _, _), y in zip(shapes_with_dtype, Y):
+        allowed = [j for j, (d, _) in enumerate(pred.table) if d == dt]
+        out.append(sorted(allowed, key=lambda j: -y[j])[:k])
+    return out
+
+
 def single_best_baseline(ds: Dataset, table) -> dict:
     """Per dtype: the slot with the best geometric-mean relative speed over the
     dataset (one tuned configuration per dtype, the paper's tuning outcome)."""
@@ -312,3 +330,51 @@ def top_k_fallback(ds: Dataset, pred: Predictor, k=3) -> np.ndarray:
     Y = np.where(ds.M > 0, Y, -np.inf)
     top = np.argsort(-Y, axis=1)[:, :k]
     return np.array([max(ds.T[i, j] for j in top[i] if ds.M[i, j] > 0) for i in range(len(top))])
+
+
+# Training settings of the shipped model (paper_1706_10086_amd/data/model.mlp):
+# 8000 Adam steps at 3e-3, 4000 more at 1e-3, targets r^4, seed 5.
+TRAIN_SETTINGS = dict(steps=8000, lr=3e-3, final_steps=4000, final_lr=1e-3)
+# The tuner's shape sets the model trains on (FP64 and FP32 each): the 3000
+# 'train' shapes and the 800 'aligned' ones (the same law, dimensions rounded up
+# to multiples of 4, which the random draws rarely give); the 500 'heldout'
+# shapes stay out and score it.
+TRAIN_SETS = ("train", "aligned")
+
+
+def datasets(db, table):
+    """(training rows, held-out rows) of ``db`` for ``table``: FP64 and FP32 on
+    the TRAIN_SETS shapes and on the held-out shapes."""
+    from . import tune
+    tr = [(dt, *s) for dt in (F64, F32) for name in TRAIN_SETS for s in tune.shape_set(name)]
+    ho = [(dt, *s) for dt in (F64, F32) for s in tune.shape_set("heldout")]
+    return build_dataset(db, table, tr), build_dataset(db, table, ho)
+
+
+def main(argv=None):
+    """Trains the predictor on a tuner database (the compact .json.gz form or a
+    JSONL database) with the library's kernels and writes the model file that
+    mgemm_model_load and the chooser read; prints the held-out scores."""
+    import argparse
+    from . import tune
+    ap = argparse.ArgumentParser(description="train the tile-configuration predictor")
+    ap.add_argument("--db", required=True)
+    ap.add_argument("--out", required=True)
+    a = ap.parse_args(argv)
+    db = tune.load_compact(a.db) if a.db.endswith(".gz") else tune.DB.load(a.db)
+    table = config_table()
+    dtr, dho = datasets(db, table)
+    if not dtr.shapes:
+        raise SystemExit("the database has no training rows for the registered configurations")
+    pred = train(dtr, table, log=lambda s: print(s, flush=True), **TRAIN_SETTINGS)
+    pred.save(a.out)
+    print(f"learn: wrote {a.out} ({len(dtr.shapes)} training rows, {len(table)} outputs)", flush=True)
+    if dho.shapes:
+        base = single_best_baseline(dtr, table)
+        print("held-out, model:", summarize(achieved(dho, predict(pred, dho.shapes))), flush=True)
+        print("held-out, one configuration per dtype:",
+              summarize(achieved(dho, [base[s[0]] for s in dho.shapes])), flush=True)
+
+
+if __name__ == "__main__":
+    main()

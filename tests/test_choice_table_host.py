@@ -28,7 +28,7 @@ def test_committed_table_matches_the_generator(db):
         assert f.read() == text
 
 
-@pytest.mark.parametrize("whole,floor", [(False, 0.95), (True, 0.90)])
+@pytest.mark.parametrize("whole,floor", [(False, 0.92), (True, 0.92)])
 def test_table_beats_the_preference_list_on_held_out_shapes(db, whole, floor):
     tables = gen.build_tables(db.records, gen.training_shapes())
     held = set(tune.shape_set("heldout"))

@@ -23,18 +23,15 @@ def data():
         pytest.skip("no GPU")
     db = tune.load_compact(DB_PATH)
     table = learn.config_table()
-    tr = [(dt, *s) for dt in (mg.F64, mg.F32) for s in tune.shape_set("train")]
-    ho = [(dt, *s) for dt in (mg.F64, mg.F32) for s in tune.shape_set("heldout")]
-    dtr = learn.build_dataset(db, table, tr)
-    dho = learn.build_dataset(db, table, ho)
-    assert len(dtr.shapes) == 6000 and len(dho.shapes) == 1000, "database does not match registry"
+    dtr, dho = learn.datasets(db, table)
+    assert len(dtr.shapes) == 7600 and len(dho.shapes) == 1000, "database does not match registry"
     return table, dtr, dho
 
 
 def test_mlp_regret_within_5_percent_and_beats_single_config(data):
     table, dtr, dho = data
     print("training the predictor", flush=True)
-    pred = learn.train(dtr, table, steps=6000, lr=2e-3)
+    pred = learn.train(dtr, table, **learn.TRAIN_SETTINGS)
     assert pred.history[-1][1] < pred.history[0][1]
     choice = learn.predict(pred, dho.shapes)
     mlp = learn.summarize(learn.achieved(dho, choice))
@@ -42,12 +39,19 @@ def test_mlp_regret_within_5_percent_and_beats_single_config(data):
     single = learn.summarize(learn.achieved(dho, [base[s[0]] for s in dho.shapes]))
     top3 = learn.summarize(learn.top_k_fallback(dho, pred, 3))
     print(f"  mlp {mlp}\n  single {single}\n  top3 {top3}", flush=True)
+    # within 5 % of the exhaustive best over the 244 configurations, far above
+    # the paper's one tuned configuration per dtype; measuring the three best
+    # predictions comes within 3 %
     assert mlp["geomean"] >= 0.95
-    assert mlp["geomean"] > single["geomean"]
-    assert top3["geomean"] >= mlp["geomean"]
+    assert mlp["geomean"] > single["geomean"] + 0.1
+    assert top3["geomean"] >= max(mlp["geomean"], 0.97)
     for dt in (mg.F64, mg.F32):
         rows = [i for i, s in enumerate(dho.shapes) if s[0] == dt]
-        assert learn.summarize(learn.achieved(dho, choice)[rows])["geomean"] >= 0.95
+        assert learn.summarize(learn.achieved(dho, choice)[rows])["geomean"] >= 0.94
+    # the shipped model file is this training run's result
+    shipped = learn.Predictor.load(os.path.join(os.path.dirname(DB_PATH), "model.mlp"),
+                                   check_table=table)
+    assert np.array_equal(shipped.params, pred.params)
 
 
 def test_predictions_are_valid_configurations(data):
@@ -68,21 +72,24 @@ def test_predictions_are_valid_configurations(data):
 
 def test_chooser_database_then_model():
     """The run-time chooser: a swept shape takes its database best, an unseen
-    shape the model's prediction; the product is correct either way."""
+    shape the model's prediction (or, measuring the model's three best, the
+    fastest of them); the product is correct every way."""
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     import oracle
     import synth
     from paper_1706_10086_amd import choose
     ch = choose.ConfigChooser()
+    chm = choose.ConfigChooser(measure_top=3)
     seen = tune.shape_set("heldout")[0]
-    for i, ((m, n, k), want) in enumerate(((seen, "database"), ((333, 517, 271), "model"))):
-        print(f"chooser shape {(m, n, k)}", flush=True)
+    for i, ((m, n, k), want, c) in enumerate(((seen, "database", ch), ((333, 517, 271), "model", ch),
+                                              ((333, 517, 271), "measured", chm))):
+        print(f"chooser shape {(m, n, k)} {want}", flush=True)
         A = synth.uniform_pm1((m, k), 610 + 2 * i)
         B = synth.uniform_pm1((k, n), 611 + 2 * i)
         C = torch.zeros((m, n), dtype=torch.float64, device="cuda")
         _, source = choose.tuned_gemm(torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda(), C,
-                                      chooser=ch)
+                                      chooser=c)
         torch.cuda.synchronize()
         assert source == want
         ref = oracle.gemm_f64(1.0, A, B, 0.0, None, nthreads=oracle.num_procs())

@@ -247,3 +247,14 @@ def test_refinement_records_replace_the_sweeps_measurements(tmp_path):
         assert cfg == (2, 2, 2, 2, 2, 2, 2) and tf == pytest.approx(fl / (0.97e-3) / 1e12)
         assert d.shapes_done("d") == {(0, 100, 200, 300)}
         assert d.shapes_refined("d") == {(0, 100, 200, 300)}
+
+
+def test_shipped_model_file_matches_the_registry():
+    """The shipped model file parses (checksum, syntax), has one output per
+    registered configuration in registry order, and standardises the six inputs."""
+    path = os.path.join(os.path.dirname(tune.__file__), "data", "model.mlp")
+    pred = learn.Predictor.load(path, check_table=learn.config_table())
+    assert len(pred.mean) == 6 and len(pred.std) == 6 and pred.hidden == 64
+    I, H, O = 6, 64, len(pred.table)
+    assert pred.params.size == H * I + H + H * H + H + O * H + O
+    assert np.all(np.isfinite(pred.params))
