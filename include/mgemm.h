@@ -109,16 +109,18 @@ MGEMM_API int32_t gemm(int64_t m, int64_t n, int64_t k, double alpha,
  * a hipStream_t; NULL: the current library stream).
  *
  * The library's choice (MGEMM_F64, MGEMM_F32): the largest preferred tile that
- * still gives enough work-groups for the m x n output; split-k below; then, with
- * m, n, k in [64, 16384], for rows the three-stage kernels cannot load (n, lda, ldb
- * not multiples of 16 bytes, or A, B not 16-byte aligned), or where the preferred
- * tile is a two-stage one, the configuration measured fastest on the tuner's shapes
- * of the same row class and (floor(log2 m), floor(log2 n), floor(log2 k)) cell.
- * With a cost model loaded (mgemm_model_load), its prediction replaces the last
- * two steps.
+ * still gives enough work-groups for the m x n output; split-k below where k >=
+ * 2048 or m, n or k lies outside [64, 16384]; otherwise (with m, n, k in
+ * [64, 16384]), for rows the three-stage kernels cannot load (n, lda, ldb not
+ * multiples of 16 bytes, or A, B not 16-byte aligned), or where the preferred
+ * tile is a two-stage one, the configuration measured fastest on the tuner's
+ * shapes of the same row class in and around the (floor(log2 m), floor(log2 n),
+ * floor(log2 k)) cell.  With a cost model loaded (mgemm_model_load), its
+ * prediction replaces that last step and the preferred tile.
  *
- * Split-k (MGEMM_F64 and MGEMM_F32, cfg == NULL only): when the chosen tile
- * leaves fewer than about four work-groups per compute unit and k >= 512, k is
+ * Split-k (MGEMM_F64 and MGEMM_F32, cfg == NULL only, k >= 2048 or outside the
+ * measured range): when the preferred tile leaves fewer than about four
+ * work-groups per compute unit and k >= 512, k is
  * cut into S <= 16 ranges (multiples of 256; computed with the three-stage
  * 128 x 128 tile where its requirements hold and it fills the GPU, else, for
  * MGEMM_F64 only, with the chosen tile); their partial products go to the library-owned
@@ -290,8 +292,9 @@ MGEMM_API int32_t mlp_save(void *mlp, const char *path, const int32_t *out_dtype
  * searches its tuning parameters exhaustively per architecture (Sec. 3, Tab. 4)
  * and names that tuning as the cost that grows with the parameters (Sec. 6); with
  * a model loaded, gemm_ex with cfg == NULL (MGEMM_F64, MGEMM_F32) runs the
- * model's prediction for the shape instead of the built-in table, except where
- * the built-in choice cuts k (split-k: no model output stands for it).  The
+ * model's prediction for shapes with m, n, k in [64, 16384] (the range it
+ * learned) instead of the built-in table, except where the built-in choice cuts
+ * k (split-k: no model output stands for it).  The
  * first such call for a shape evaluates the network on the current device with
  * the library's kernels and waits for it (calls on a stream being captured into a
  * graph use a prediction only if one is already cached);

@@ -594,7 +594,7 @@ hipError_t launch_pipe(const GemmArgs &a, hipStream_t s) {
 // A two-stage configuration that also runs split-k for the built-in choice (FP64
 // only: at N = 1024 it raised FP64 from 27.0 to 30.9 TFLOP/s, while FP32, twice as
 // fast per tile, lost 4 % to the extra reduction).
-#define MGEMM_CFG_SPLITK(T, BM, BN, BK, WGM, WGN, EPT, DBUF, OCC)                       \
+#define MGEMM_REG_SPLITK(T, BM, BN, BK, WGM, WGN, EPT, DBUF, OCC)                       \
     {{BM, BN, BK, WGM * WGN, EPT, DBUF, OCC},                                             \
      &launch_tiled<T, BM, BN, BK, WGM, WGN, EPT, DBUF, OCC, true>,                        \
      &launch_tiled<T, BM, BN, BK, WGM, WGN, EPT, DBUF, OCC, false>,                       \
@@ -619,9 +619,9 @@ static const KernelEntry kF64[] = {
     MGEMM_CFG(double, 128, 256, 16, 2, 4, 2, 1, 0),
     MGEMM_CFG(double, 128, 64, 16, 2, 2, 2, 1, 0),
     MGEMM_CFG(double, 128, 64, 32, 2, 2, 4, 0, 2),
-    MGEMM_CFG_SPLITK(double, 64, 64, 16, 2, 2, 2, 1, 0),
+    MGEMM_REG_SPLITK(double, 64, 64, 16, 2, 2, 2, 1, 0),
     MGEMM_CFG(double, 64, 64, 32, 2, 2, 2, 1, 0),
-    MGEMM_CFG_SPLITK(double, 32, 32, 16, 1, 1, 2, 1, 0),
+    MGEMM_REG_SPLITK(double, 32, 32, 16, 1, 1, 2, 1, 0),
     // three-stage direct-load kernels (one or two waves per SIMD; with one wave per
     // SIMD, as 128x128 with 4 waves or smaller tiles, they measured slower than the
     // two-stage kernels of the same tile, so only these two are registered)

@@ -59,7 +59,7 @@ def hand_configs(dtype: int) -> set:
     text = open(os.path.join(HERE, "gemm_tiled.hip")).read()
     tname = NAMES[dtype][1]
     out = set()
-    for kind, args in re.findall(r"^\s*(MGEMM_CFG|MGEMM_CFG_SPLITK|MGEMM_PIPE_CFG)\(([^)]*)\)",
+    for kind, args in re.findall(r"^\s*(MGEMM_CFG|MGEMM_REG_SPLITK|MGEMM_PIPE_CFG)\(([^)]*)\)",
                                  text, flags=re.M):
         a = [x.strip() for x in args.split(",")]
         if a[0] != tname:
@@ -100,7 +100,8 @@ def render(dtype: int) -> dict:
         lines = [
             f"// Tuning-grid kernels ({short.upper()}), part {part} of {PARTS}: written by "
             "gen_grid.py, do not edit.",
-            "// Each entry: (bm, bn, bk, waves, elements per thread, stages - 1, occupancy) with",
+            "// Each entry: (bm, bn, bk, waves along m, waves along n, elements per thread,",
+            "// stages - 1, occupancy) with",
             "// the two-stage kernel for aligned and for any rows (tile_gemm.h).",
             '#include "tile_gemm.h"',
             "",

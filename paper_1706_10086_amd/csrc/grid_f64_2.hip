@@ -1,5 +1,6 @@
 // Tuning-grid kernels (F64), part 2 of 4: written by gen_grid.py, do not edit.
-// Each entry: (bm, bn, bk, waves, elements per thread, stages - 1, occupancy) with
+// Each entry: (bm, bn, bk, waves along m, waves along n, elements per thread,
+// stages - 1, occupancy) with
 // the two-stage kernel for aligned and for any rows (tile_gemm.h).
 #include "tile_gemm.h"
 

@@ -166,10 +166,15 @@ static const KernelEntry *find_entry(const KernelEntry *reg, int cnt, const mgem
 // (rows16) or are not whole 16-byte loads (choice_table.h: the tuner database's
 // shapes of the same class and log2 cell); NULL outside the table's range or for
 // an unlisted cell.
+// Whether m, n, k lie in the range the tuner's shapes cover ([64, 16384]).
+static bool in_measured_range(int64_t m, int64_t n, int64_t k) {
+    constexpr int64_t lo = (int64_t)1 << CHOICE_LOG2_LO, hi = (int64_t)1 << CHOICE_LOG2_HI;
+    return m >= lo && n >= lo && k >= lo && m <= hi && n <= hi && k <= hi;
+}
+
 static const KernelEntry *measured_entry(int32_t dtype, bool rows16, int64_t m, int64_t n,
                                          int64_t k) {
-    constexpr int64_t lo = (int64_t)1 << CHOICE_LOG2_LO, hi = (int64_t)1 << CHOICE_LOG2_HI;
-    if (m < lo || n < lo || k < lo || m > hi || n > hi || k > hi) return nullptr;
+    if (!in_measured_range(m, n, k)) return nullptr;
     auto lg = [](int64_t x) { int l = 0; while (x >> (l + 1)) ++l; return l; };
     const ChoiceCell key = {(int8_t)dtype, (int8_t)(rows16 ? 1 : 0), (int8_t)lg(m),
                             (int8_t)lg(n), (int8_t)lg(k)};
@@ -249,8 +254,12 @@ static bool capturing(hipStream_t s) {
     return st != hipStreamCaptureStatusNone;
 }
 
-// Split-k for the built-in choice: when that fell back to a 64 x 64 or 32 x 32
-// tile and still leaves fewer than about four work-groups per compute unit, k is
+// Split-k for the built-in choice, before the measured choice for k >= 2048 and for
+// shapes outside the measured range (m, n or k outside [64, 16384]); below that k
+// the measured configurations, run whole, were faster (on 200 held-out FP64 shapes:
+// split first for k >= 2048 only 0.990 of the better of the two per shape, split
+// first always 0.932, never 0.917): when the preferred tile is a 64 x 64 or 32 x 32
+// one and still leaves fewer than about four work-groups per compute unit, k is
 // cut into S ranges of kc values (a multiple of SPLITK_MIN_K, itself a multiple of
 // every tile's BK; the last range is the short one); the S partial products go to
 // the library workspace and one reduction kernel adds them in order and applies
@@ -260,6 +269,7 @@ static bool capturing(hipStream_t s) {
 // two-stage tile with about four work-groups per compute unit (for FP32, twice as
 // fast per tile, that lost 4 % to the extra reduction, so FP32 then runs whole).
 constexpr int64_t SPLITK_MIN_K = 256;
+constexpr int64_t SPLITK_FIRST_K = 2048;
 constexpr int SPLITK_MAX = 16;
 
 static int compute_units() {
@@ -335,12 +345,14 @@ int32_t plan_call(const GemmArgs &a, int32_t dtype, const mgemm_cfg *cfg,
     const KernelEntry *e = choose_entry(dtype, a.m, a.n, cfg, &err);
     if (!e) return err;
     cp.al = rows_aligned(a.A, a.lda, a.B, a.ldb, dtype);
-    if (!cfg) {
+    const bool in_range = in_measured_range(a.m, a.n, a.k);
+    if (!cfg && (!in_range || a.k >= SPLITK_FIRST_K)) {
+        // the preferred tile with k cut into ranges where that tile leaves the GPU
+        // short of work: outside the range the tuner measured (and the model
+        // learned), and inside it for long k
         cp.sp = splitk_plan(a, e, dtype);
-        if (cp.sp.S > 1) {
-            cp.e = e;
-            return 0;
-        }
+    }
+    if (!cfg && in_range && cp.sp.S == 1) {
         // a loaded cost model's choice (evaluated on the device once per shape)
         mgemm_cfg mc;
         const KernelEntry *me = nullptr;
@@ -351,16 +363,16 @@ int32_t plan_call(const GemmArgs &a, int32_t dtype, const mgemm_cfg *cfg,
         }
         g_err.clear();     // a model that could not be used leaves the built-in choice
         if (me) {
-            e = me;
-        } else {
-            // the configuration measured fastest for shapes like this one: always for
-            // rows the three-stage kernels cannot load (which the preference list
-            // favours), else where the list names a two-stage configuration
-            const bool rows16 = rows_whole_loads(a, dtype);
-            if (!rows16 || e->cfg.double_buffer != 2) {
-                const KernelEntry *t = measured_entry(dtype, rows16, a.m, a.n, a.k);
-                if (t) e = t;
-            }
+            cp.e = me;
+            return 0;
+        }
+        // the configuration measured fastest for shapes like this one: always for
+        // rows the three-stage kernels cannot load (which the preference list
+        // favours), else where the list names a two-stage configuration
+        const bool rows16 = rows_whole_loads(a, dtype);
+        if (!rows16 || e->cfg.double_buffer != 2) {
+            const KernelEntry *t = measured_entry(dtype, rows16, a.m, a.n, a.k);
+            if (t) e = t;
         }
     }
     cp.e = e;

@@ -177,17 +177,20 @@ def test_fp32_within_gamma_bound(dev, orc):
 
 # the first four take the three-stage 128 x 128 tile for the k ranges (the last
 # with a ragged final range: 512 + 512 + 76), the others the 64 x 64 or 32 x 32 tile
-SPLITK_SHAPES = [(1024, 1024, 1024), (896, 1024, 1536), (1024, 512, 4096), (1024, 1024, 1100),
-                 (1000, 999, 3001), (37, 45, 5000), (64, 1024, 777), (1, 1, 70000),
-                 (300, 200, 600), (511, 130, 513)]
+# shapes the built-in choice runs with k cut (k >= 2048, or outside the measured
+# range), and some it runs whole (the measured configuration) since k is short
+SPLITK_SHAPES = [(1024, 512, 4096), (1000, 999, 3001), (300, 200, 6000), (511, 130, 2513),
+                 (37, 45, 5000), (1, 1, 70000), (64, 1024, 2777), (1024, 1024, 1024),
+                 (896, 1024, 1536), (300, 200, 600)]
 
 
 @pytest.mark.parametrize("dtype", [mg.F64, mg.F32])
 def test_split_k_default_choice(dev, orc, dtype):
-    """Outputs whose chosen tile leaves fewer than about four work-groups per
-    compute unit, with k >= 512, run split-k under the built-in choice (k cut into
-    ranges of 256j, partial products reduced in order; FP32 only on the
-    three-stage tile, whose rows must be 16-byte aligned): every element within
+    """Outputs whose preferred tile leaves fewer than about four work-groups per
+    compute unit, with k >= 2048 (or outside the measured range), run split-k
+    under the built-in choice (k cut into ranges of 256j, partial products reduced
+    in order; FP32 only on the three-stage tile, whose rows must be 16-byte
+    aligned); shorter k runs the measured configuration whole: every element within
     gamma_{k+2} of the double-double oracle, FP64 normwise <= 1e-13, run-to-run
     identical, C not read when beta = 0."""
     u = 2.0 ** -24 if dtype == mg.F32 else 2.0 ** -53
@@ -209,24 +212,24 @@ def test_split_k_default_choice(dev, orc, dtype):
         assert np.array_equal(got, again)
         nan_c = run_gemm(dev, A, B, np.full((m, n), np.nan), 1.5, 0.0, dtype=dtype)
         assert np.all(np.isfinite(nan_c))
-    # the 1024^3 product really took the split path: its summation order differs from
-    # the same tile run whole (an explicit configuration never splits k)
-    n = 1024
-    A = synth.uniform_pm1((n, n), 31)
-    B = synth.uniform_pm1((n, n), 32)
+    # the 1024 x 512 x 4096 product really took the split path: its summation order
+    # differs from the same tile run whole (an explicit configuration never splits k)
+    n, k = 1024, 4096
+    A = synth.uniform_pm1((n, k), 31)
+    B = synth.uniform_pm1((k, n // 2), 32)
     if dtype == mg.F32:
         A, B = (x.astype(np.float32).astype(np.float64) for x in (A, B))
     whole_cfg = [c for c in mg.configs(dtype) if (c.bm, c.bn, c.bk, c.waves) == (64, 64, 16, 4)][0]
-    split = run_gemm(dev, A, B, np.zeros((n, n)), 1.0, 0.0, dtype=dtype)
-    whole = run_gemm(dev, A, B, np.zeros((n, n)), 1.0, 0.0, dtype=dtype, cfg=whole_cfg)
+    split = run_gemm(dev, A, B, np.zeros((n, n // 2)), 1.0, 0.0, dtype=dtype)
+    whole = run_gemm(dev, A, B, np.zeros((n, n // 2)), 1.0, 0.0, dtype=dtype, cfg=whole_cfg)
     assert not np.array_equal(split, whole)
-    assert np.linalg.norm(split - whole) <= 4 * n * u * np.linalg.norm(whole)
+    assert np.linalg.norm(split - whole) <= 4 * k * u * np.linalg.norm(whole)
     if dtype == mg.F32:
         return
     # the same k ranges on the two-stage tile (an odd leading dimension of A rules
     # out the three-stage kernel): every tile sums a range in the same order, so
     # both splits agree bit for bit
-    for k in (1024, 1100):
+    for k in (4096, 4100):
         A = synth.uniform_pm1((n, k), 33 + k)
         B = synth.uniform_pm1((k, n), 34 + k)
         tA, tB = to_dev(A, dev), to_dev(B, dev)

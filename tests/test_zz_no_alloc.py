@@ -38,9 +38,10 @@ def call(fn, tA, tB, tC, alpha, beta, dtype, cfg=None):
     assert rc == 0, mg.last_error()
 
 
-# (m, n, k): the first two split k (N = 1024 square, and a smaller output with
-# long k), the third is too large to split, the fourth has odd rows
-CASES = [(1024, 1024, 1024), (384, 256, 3000), (2048, 2048, 512), (333, 271, 1517)]
+# (m, n, k): the first two split k (on the three-stage tile in both dtypes, and
+# on the two-stage tile in FP64), the third is too large to split, the fourth has
+# odd rows and a short k (the measured configuration, run whole)
+CASES = [(1024, 512, 4096), (384, 256, 3000), (2048, 2048, 512), (333, 271, 1517)]
 
 
 @pytest.mark.parametrize("dtype", [mg.F64, mg.F32])
