@@ -116,6 +116,29 @@ def timed(fn, stream, reps, warmup=1):
     return [ev[i].elapsed_time(ev[i + 1]) for i in range(reps)]
 
 
+def timed_batches(fn, stream, batches=5, warm_s=0.1, batch_s=0.05):
+    """Per-call device time (ms) of back-to-back calls of fn(): one event pair
+    around each batch of calls (events between every call add a few microseconds
+    each, which small products would count); warmed up for warm_s seconds first
+    (clocks ramp up) and each batch sized to about batch_s seconds."""
+    import torch
+    est = timed(fn, stream, 3, warmup=2)
+    per = max(min(est), 1e-3) / 1e3
+    for _ in range(max(3, int(warm_s / per))):
+        fn()
+    reps = max(3, int(batch_s / per))
+    out = []
+    for _ in range(batches):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        out.append(e0.elapsed_time(e1) / reps)
+    return out
+
+
 def cpu_baseline(n, A, B, C, budget_s):
     """Times the oracle on a row sample of the same product; scales to TFLOP/s."""
     import oracle
@@ -229,7 +252,10 @@ def leg_sweep(mg, torch, dev, sizes=(1024, 2048, 4096, 8192, 16384)):
     uniform[-1,1) inputs drawn on the device, alpha = beta = 1."""
     log("bench: square sweep, FP64 and FP32")
     stream = torch.cuda.current_stream()
-    out = {"inputs": "uniform[-1,1) on the device, alpha = beta = 1", "f64": {}, "f32": {}}
+    out = {"inputs": "uniform[-1,1) on the device, alpha = beta = 1",
+           "timing": "back-to-back calls after 0.1 s of warm-up, one event pair per batch "
+                     "of about 50 ms; ms = mean over the batches",
+           "f64": {}, "f32": {}}
     for name, tdt, dt, peak in (("f64", torch.float64, mg.F64, PEAK_F64_TFLOPS),
                                 ("f32", torch.float32, mg.F32, PEAK_F32_TFLOPS)):
         for n in sizes:
@@ -238,8 +264,8 @@ def leg_sweep(mg, torch, dev, sizes=(1024, 2048, 4096, 8192, 16384)):
             A = torch.rand((n, n), device=dev, dtype=tdt, generator=g) * 2 - 1
             B = torch.rand((n, n), device=dev, dtype=tdt, generator=g) * 2 - 1
             C = torch.rand((n, n), device=dev, dtype=tdt, generator=g) * 2 - 1
-            reps = 10 if n <= 8192 else 3
-            ts = timed(lambda: mg.gemm(A, B, C, 1.0, 1.0, stream=stream), stream, reps)
+            ts = timed_batches(lambda: mg.gemm(A, B, C, 1.0, 1.0, stream=stream), stream,
+                               batches=5 if n <= 8192 else 3)
             ms = float(np.mean(ts))
             tf = 2.0 * n ** 3 / ms / 1e9
             out[name][str(n)] = {"ms": round(ms, 4), "tflops": round(tf, 3),
