@@ -277,8 +277,10 @@ MGEMM_API int32_t mlp_destroy(void *mlp);
  *   out_dtype  (host, out entries) dtype of each output, MGEMM_F64 or MGEMM_F32;
  *   out_cfg    (host, out entries) the registered configuration of each output;
  *   feat_mean, feat_std  (host, 6 doubles each, std > 0) the features x = [log2 m,
- *              log2 n, log2 k, dtype == MGEMM_F64, == MGEMM_F32, == MGEMM_SPLIT_BF16]
- *              enter the network as (x - mean) / std rounded to float.
+ *              log2 n, log2 k, dtype == MGEMM_F64, dtype == MGEMM_F32, w] enter the
+ *              network as (x - mean) / std rounded to float; w = 1 where the rows of
+ *              A and B are whole 16-byte loads (n, lda, ldb multiples of 2 in FP64,
+ *              of 4 in FP32; A and B 16-byte aligned), else 0.
  * The network must have 6 inputs.  Every value is written as a C99 hexadecimal
  * float (exact), followed by an FNV-1a checksum of the text.  Returns 0; -1..-6
  * for a NULL argument; MGEMM_ERR_MODEL (not 6 inputs, an output naming a
@@ -304,10 +306,11 @@ MGEMM_API int32_t mlp_save(void *mlp, const char *path, const int32_t *out_dtype
  * this library does not register (the model loaded before stays loaded then). */
 MGEMM_API int32_t mgemm_model_load(const char *path);
 
-/* The loaded model's configuration for an m x n x k product of dtype (the output
- * of that dtype with the largest predicted value, lowest index on ties),
- * evaluated by the library's HIP kernels on the current device (the call waits
- * for them; predictions are cached per shape).  Returns 0; -1..-3 (m, n or k
+/* The loaded model's configuration for an m x n x k product of dtype stored
+ * without padding (lda = k, ldb = n, aligned bases; the output of that dtype
+ * with the largest predicted value, lowest index on ties), evaluated by the
+ * library's HIP kernels on the current device (the call waits for them;
+ * predictions are cached per shape and row class).  Returns 0; -1..-3 (m, n or k
  * below 1), -4 (the model has no output for dtype), -5 (out NULL);
  * MGEMM_ERR_MODEL (no model loaded). */
 MGEMM_API int32_t mgemm_model_predict(int64_t m, int64_t n, int64_t k, int32_t dtype,

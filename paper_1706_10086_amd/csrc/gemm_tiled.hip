@@ -622,11 +622,13 @@ static const KernelEntry kF64[] = {
     MGEMM_REG_SPLITK(double, 64, 64, 16, 2, 2, 2, 1, 0),
     MGEMM_CFG(double, 64, 64, 32, 2, 2, 2, 1, 0),
     MGEMM_REG_SPLITK(double, 32, 32, 16, 1, 1, 2, 1, 0),
-    // three-stage direct-load kernels (one or two waves per SIMD; with one wave per
-    // SIMD, as 128x128 with 4 waves or smaller tiles, they measured slower than the
-    // two-stage kernels of the same tile, so only these two are registered)
+    // three-stage direct-load kernels: the two large tiles with two waves per SIMD,
+    // and a 64 x 64 tile with one (for products of a few hundred tiles: at 1024^3 it
+    // ran at 47 TFLOP/s against 37 for the best two-stage tile; 64 x 64 x 16 reached
+    // 40, 128 x 128 with four waves and 128 x 64 tiles 17-29)
     MGEMM_PIPE_CFG(double, 256, 128, 16, 4, 2, 4, 2, 2),
     MGEMM_PIPE_CFG(double, 128, 128, 16, 4, 2, 2, 2, 2),
+    MGEMM_PIPE_CFG(double, 64, 64, 32, 2, 2, 2, 2, 4),
 };
 
 static const KernelEntry kF32[] = {
@@ -640,6 +642,10 @@ static const KernelEntry kF32[] = {
     MGEMM_CFG(float, 32, 32, 16, 1, 1, 2, 1, 0),
     MGEMM_PIPE_CFG(float, 256, 128, 32, 4, 2, 4, 2, 4),
     MGEMM_PIPE_CFG(float, 128, 128, 32, 4, 2, 2, 2, 4),
+    // one wave per SIMD, 64 x 64 (1024^3: 89 TFLOP/s with k-steps of 64, 82 with 32,
+    // against 62 for the best two-stage tile)
+    MGEMM_PIPE_CFG(float, 64, 64, 64, 2, 2, 2, 2, 4),
+    MGEMM_PIPE_CFG(float, 64, 64, 32, 2, 2, 2, 2, 4),
 };
 
 // The hand-registered entries followed by every part of the tuning grid.

@@ -233,7 +233,7 @@ const KernelEntry *choose_entry(int32_t dtype, int64_t m, int64_t n, const mgemm
 }
 
 int32_t split_gemm(const GemmArgs &a, int32_t dtype, hipStream_t s);
-int32_t model_choose(int32_t dtype, int64_t m, int64_t n, int64_t k, bool may_launch,
+int32_t model_choose(int32_t dtype, int64_t m, int64_t n, int64_t k, bool rows16, bool may_launch,
                      mgemm_cfg *out);
 
 // Whether cfg is in dtype's registry.
@@ -356,7 +356,8 @@ int32_t plan_call(const GemmArgs &a, int32_t dtype, const mgemm_cfg *cfg,
         // a loaded cost model's choice (evaluated on the device once per shape)
         mgemm_cfg mc;
         const KernelEntry *me = nullptr;
-        if (model_choose(dtype, a.m, a.n, a.k, model_may_launch, &mc) == 0) {
+        if (model_choose(dtype, a.m, a.n, a.k, rows_whole_loads(a, dtype), model_may_launch,
+                         &mc) == 0) {
             int cnt = 0;
             const KernelEntry *reg = registry(dtype, &cnt);
             me = find_entry(reg, cnt, mc);

@@ -10,7 +10,7 @@
 //
 // File format (ASCII lines; every floating-point value as a C99 hexadecimal
 // float, so that it is read back exactly):
-//   mgemm-mlp 1
+//   mgemm-mlp 2
 //   dims <in> <hidden> <out>
 //   out <dtype> <bm> <bn> <bk> <waves> <elems_per_thread> <double_buffer> <occupancy>
 //       (one line per output, in output order)
@@ -20,7 +20,9 @@
 //   <count values, 8 per line>       W1 b1 W2 b2 W3 b3 (float), row-major
 //   checksum <16 hex digits>         FNV-1a (64-bit) of every byte before this line
 // Features of an m x n x k product of dtype d: x = [log2 m, log2 n, log2 k,
-// d == F64, d == F32, d == SPLIT_BF16], scaled as (x - mean) / std in double and
+// d == F64, d == F32, w], w = 1 where the rows of A and B are whole 16-byte loads
+// (n, lda and ldb multiples of 2 in FP64, of 4 in FP32, A and B 16-byte aligned:
+// the three-stage kernels run only then), scaled as (x - mean) / std in double and
 // rounded to float.  The prediction is the output with the largest value among
 // those whose dtype is d (lowest index on ties).
 #include <math.h>
@@ -70,7 +72,7 @@ int32_t model_write(const char *path, int I, int H, int O, const int32_t *out_dt
                     const mgemm_cfg *out_cfg, const double *mean, const double *stdv,
                     const float *params, int64_t P) {
     std::string s;
-    put(s, "mgemm-mlp 1\ndims %d %d %d\n", I, H, O);
+    put(s, "mgemm-mlp 2\ndims %d %d %d\n", I, H, O);
     for (int o = 0; o < O; ++o) {
         const mgemm_cfg &c = out_cfg[o];
         put(s, "out %d %d %d %d %d %d %d %d\n", (int)out_dtype[o], (int)c.bm, (int)c.bn, (int)c.bk,
@@ -102,7 +104,7 @@ struct Model {
     float *dx[MODEL_MAX_DEVICES] = {};
     float *dm[MODEL_MAX_DEVICES] = {};
     int32_t *didx[MODEL_MAX_DEVICES] = {};
-    std::map<std::tuple<int32_t, int64_t, int64_t, int64_t>, int> cache;
+    std::map<std::tuple<int32_t, int64_t, int64_t, int64_t, bool>, int> cache;
 };
 
 static std::mutex g_model_mtx;
@@ -141,8 +143,8 @@ static int32_t model_parse(const std::string &text, const char *path, Model *out
         return true;
     };
     long long ver = 0, I = 0, H = 0, O = 0;
-    if (!word("mgemm-mlp") || !integer(&ver) || ver != 1)
-        return set_error(MGEMM_ERR_MODEL, "model %s: not an mgemm-mlp version 1 file", path);
+    if (!word("mgemm-mlp") || !integer(&ver) || ver != 2)
+        return set_error(MGEMM_ERR_MODEL, "model %s: not an mgemm-mlp version 2 file", path);
     if (!word("dims") || !integer(&I) || !integer(&H) || !integer(&O))
         return set_error(MGEMM_ERR_MODEL, "model %s: bad dims line", path);
     if (I != MODEL_IN)
@@ -216,10 +218,10 @@ static void model_free(Model *md) {
 
 // The model's choice for a shape (caller holds g_model_mtx).  may_launch false:
 // only a cached choice is returned (MGEMM_ERR_MODEL otherwise, without text).
-static int32_t model_choose_locked(int32_t dtype, int64_t m, int64_t n, int64_t k, bool may_launch,
-                                   mgemm_cfg *out) {
+static int32_t model_choose_locked(int32_t dtype, int64_t m, int64_t n, int64_t k, bool rows16,
+                                   bool may_launch, mgemm_cfg *out) {
     Model *md = g_model;
-    const auto key = std::make_tuple(dtype, m, n, k);
+    const auto key = std::make_tuple(dtype, m, n, k, rows16);
     auto it = md->cache.find(key);
     if (it != md->cache.end()) {
         *out = md->out_cfg[it->second];
@@ -243,7 +245,7 @@ static int32_t model_choose_locked(int32_t dtype, int64_t m, int64_t n, int64_t 
     }
     const double raw[MODEL_IN] = {log2((double)m), log2((double)n), log2((double)k),
                                   dtype == MGEMM_F64 ? 1.0 : 0.0, dtype == MGEMM_F32 ? 1.0 : 0.0,
-                                  dtype == MGEMM_SPLIT_BF16 ? 1.0 : 0.0};
+                                  rows16 ? 1.0 : 0.0};
     float x[MODEL_IN];
     for (int i = 0; i < MODEL_IN; ++i) x[i] = (float)((raw[i] - md->mean[i]) / md->stdv[i]);
     std::vector<float> mask((size_t)md->O);
@@ -266,12 +268,13 @@ static int32_t model_choose_locked(int32_t dtype, int64_t m, int64_t n, int64_t 
 // gemm_ex's use of a loaded model: 0 with *out set, or nonzero (no model, no
 // cached choice when may_launch is false, or a failed evaluation) -- the caller
 // then keeps the built-in choice.
-int32_t model_choose(int32_t dtype, int64_t m, int64_t n, int64_t k, bool may_launch,
+int32_t model_choose(int32_t dtype, int64_t m, int64_t n, int64_t k, bool rows16, bool may_launch,
                      mgemm_cfg *out) {
     std::lock_guard<std::mutex> lock(g_model_mtx);
     if (!g_model) return MGEMM_ERR_MODEL;
     for (int o = 0; o < g_model->O; ++o)
-        if (g_model->out_dtype[o] == dtype) return model_choose_locked(dtype, m, n, k, may_launch, out);
+        if (g_model->out_dtype[o] == dtype)
+            return model_choose_locked(dtype, m, n, k, rows16, may_launch, out);
     return MGEMM_ERR_MODEL;
 }
 
@@ -320,7 +323,9 @@ int32_t mgemm_model_predict(int64_t m, int64_t n, int64_t k, int32_t dtype, mgem
     bool has = false;
     for (int o = 0; o < g_model->O && !has; ++o) has = g_model->out_dtype[o] == dtype;
     if (!has) return set_error(-4, "the loaded model has no output for dtype %d", dtype);
-    return model_choose_locked(dtype, m, n, k, true, out);
+    // rows of a product stored without padding (lda = k, ldb = n)
+    const int64_t epu = dtype == MGEMM_F32 ? 4 : 2;
+    return model_choose_locked(dtype, m, n, k, n % epu == 0 && k % epu == 0, true, out);
 }
 
 }  // extern "C"

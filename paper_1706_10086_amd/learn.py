@@ -7,8 +7,11 @@ small network that predicts, for an unseen shape, the relative speed of every
 configuration; the configuration with the highest prediction is used, and the
 exhaustive sweep remains the fallback and the measure of the prediction's regret.
 
-* features  x = [log2 m, log2 n, log2 k, onehot(F64, F32, split-BF16)], scaled
-            by the training set's mean and standard deviation;
+* features  x = [log2 m, log2 n, log2 k, dtype == F64, dtype == F32, w], w = 1
+            where the rows of A and B are whole 16-byte loads (only then do the
+            three-stage configurations run their own kernels; the tuner's shapes
+            are stored without padding, lda = k, ldb = n), scaled by the training
+            set's mean and standard deviation;
 * targets   r_c^p with r_c = TFLOP/s(c) / max_c' TFLOP/s(c') for every
             configuration c of the shape's dtype (a masked multi-output
             regression; configurations of other dtypes are masked out); the power
@@ -32,9 +35,9 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from . import F32, F64, SPLIT_BF16, MLP, configs
+from . import F32, F64, MLP, configs
 
-DTYPES = (F64, F32, SPLIT_BF16)
+DTYPES = (F64, F32)
 
 
 def config_table():
@@ -51,9 +54,20 @@ def table_hash(table) -> str:
     return hashlib.sha1(json.dumps([[d, list(c)] for d, c in table]).encode()).hexdigest()[:12]
 
 
+def rows_whole_loads(n, k, dtype, lda=None, ldb=None) -> bool:
+    """Whether the rows of A (lda, default k) and B (ldb, default n) are whole
+    16-byte loads: n, lda, ldb multiples of 2 (FP64) or 4 (FP32)."""
+    epu = 4 if dtype == F32 else 2
+    lda = k if lda is None else lda
+    ldb = n if ldb is None else ldb
+    return n % epu == 0 and lda % epu == 0 and ldb % epu == 0
+
+
 def raw_features(m, n, k, dtype) -> np.ndarray:
+    """Features of a product stored without padding (lda = k, ldb = n)."""
     oh = [1.0 if dtype == d else 0.0 for d in DTYPES]
-    return np.array([math.log2(m), math.log2(n), math.log2(k)] + oh, dtype=np.float64)
+    w = 1.0 if rows_whole_loads(n, k, dtype) else 0.0
+    return np.array([math.log2(m), math.log2(n), math.log2(k)] + oh + [w], dtype=np.float64)
 
 
 @dataclass
@@ -120,7 +134,7 @@ def model_text(table, mean, std, hidden, params) -> str:
     """The model file for a 6-input network with ``hidden`` units and one output
     per (dtype, configuration tuple) of ``table``."""
     params = np.asarray(params, dtype=np.float32)
-    lines = ["mgemm-mlp 1", f"dims {len(mean)} {hidden} {len(table)}"]
+    lines = ["mgemm-mlp 2", f"dims {len(mean)} {hidden} {len(table)}"]
     lines += ["out " + " ".join(str(int(v)) for v in (dt, *c)) for dt, c in table]
     lines.append("mean " + " ".join(c_hex(v) for v in mean))
     lines.append("std " + " ".join(c_hex(v) for v in std))
@@ -140,8 +154,8 @@ def parse_model_text(text: str):
     if int(text[cpos + 9:].split()[0], 16) != fnv1a64(text[:cpos].encode()):
         raise ValueError("checksum mismatch (corrupt file)")
     tok = text[:cpos].split()
-    if tok[:2] != ["mgemm-mlp", "1"] or tok[2] != "dims":
-        raise ValueError("not an mgemm-mlp version 1 file")
+    if tok[:2] != ["mgemm-mlp", "2"] or tok[2] != "dims":
+        raise ValueError("not an mgemm-mlp version 2 file")
     I, H, O = (int(t) for t in tok[3:6])
     pos = 6
     table = []
@@ -336,10 +350,10 @@ def top_k_fallback(ds: Dataset, pred: Predictor, k=3) -> np.ndarray:
 # 8000 Adam steps at 3e-3, 4000 more at 1e-3, targets r^4, seed 5.
 TRAIN_SETTINGS = dict(steps=8000, lr=3e-3, final_steps=4000, final_lr=1e-3)
 # The tuner's shape sets the model trains on (FP64 and FP32 each): the 3000
-# 'train' shapes and the 800 'aligned' ones (the same law, dimensions rounded up
-# to multiples of 4, which the random draws rarely give); the 500 'heldout'
-# shapes stay out and score it.
-TRAIN_SETS = ("train", "aligned")
+# 'train' and 3000 'train2' shapes and the 800 'aligned' ones (the same law,
+# dimensions rounded up to multiples of 4, which the random draws rarely give);
+# the 500 'heldout' shapes stay out and score it.
+TRAIN_SETS = ("train", "train2", "aligned")
 
 
 def datasets(db, table):

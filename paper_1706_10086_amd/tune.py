@@ -361,13 +361,15 @@ def regret(db: DB, dtype: int, m: int, n: int, k: int, cfg) -> float:
 TRAIN_SEEDS = (5001, 5002, 5003)
 HELDOUT_SEEDS = (5011, 5012, 5013)
 ALIGNED_SEEDS = (5021, 5022, 5023)
+TRAIN2_SEEDS = (5031, 5032, 5033)
 
 
 def shape_set(which: str, count: int | None = None, lo: int = 64, hi: int = 16384):
-    """'train' (3000 shapes), 'heldout' (500 shapes, none also in 'train') or
+    """'train' (3000 shapes), 'heldout' (500 shapes, none also in 'train'),
     'aligned' (800 shapes rounded up to multiples of 4, so every row is a whole
-    16-byte load in FP64 and FP32; none in the other two sets): m, n, k each
-    log-uniform in [lo, hi] from their own seeded streams."""
+    16-byte load in FP64 and FP32; none in the other two sets) or 'train2' (3000
+    more training shapes, none in the other three sets): m, n, k each log-uniform
+    in [lo, hi] from their own seeded streams."""
     import synth
     if which == "train":
         seeds, cnt = TRAIN_SEEDS, 3000 if count is None else count
@@ -375,17 +377,21 @@ def shape_set(which: str, count: int | None = None, lo: int = 64, hi: int = 1638
         seeds, cnt = HELDOUT_SEEDS, 500 if count is None else count
     elif which == "aligned":
         seeds, cnt = ALIGNED_SEEDS, 800 if count is None else count
+    elif which == "train2":
+        seeds, cnt = TRAIN2_SEEDS, 3000 if count is None else count
     else:
         raise ValueError(which)
     ms, ns, ks = (synth.log_uniform_int(cnt + 64, s, lo, hi) for s in seeds)
     shapes = [(int(a), int(b), int(c)) for a, b, c in zip(ms, ns, ks)]
     if which == "aligned":
         shapes = [tuple(-(-x // 4) * 4 for x in sh) for sh in shapes]
-    if which in ("heldout", "aligned"):
-        tr = set(shape_set("train", lo=lo, hi=hi))
-        if which == "aligned":
-            tr |= set(shape_set("heldout", lo=lo, hi=hi))
-        shapes = [s for s in shapes if s not in tr]
+    if which != "train":
+        taken = set(shape_set("train", lo=lo, hi=hi))
+        if which in ("aligned", "train2"):
+            taken |= set(shape_set("heldout", lo=lo, hi=hi))
+        if which == "train2":
+            taken |= set(shape_set("aligned", lo=lo, hi=hi))
+        shapes = [s for s in shapes if s not in taken]
     out, seen = [], set()
     for s in shapes:
         if s not in seen:
@@ -594,7 +600,7 @@ def tune_batch(As, Bs, Cs, alphas=1.0, betas=0.0, dtype=F64, rules=None, reps=5,
 def main(argv=None):
     import argparse
     ap = argparse.ArgumentParser(description="autotuner sweep (resumable JSONL database)")
-    ap.add_argument("--set", choices=["train", "heldout", "aligned"], required=True)
+    ap.add_argument("--set", choices=["train", "heldout", "aligned", "train2"], required=True)
     ap.add_argument("--dtype", choices=["f64", "f32"], required=True)
     ap.add_argument("--db", required=True)
     ap.add_argument("--count", type=int, default=None)

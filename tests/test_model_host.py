@@ -85,6 +85,15 @@ def test_library_loads_valid_and_rejects_bad_files(L, tmp_path):
     (tmp_path / "p.mlp").write_text(tp)
     assert L.mgemm_model_load(str(tmp_path / "p.mlp").encode()) == mg.ERR_MODEL
     assert "parameter count" in mg.last_error()
+    # a file of the earlier format (its sixth feature flagged SPLIT_BF16, not the
+    # row alignment)
+    body = good[:good.index("checksum ")].replace("mgemm-mlp 2", "mgemm-mlp 1", 1)
+    v1 = body + f"checksum {learn.fnv1a64(body.encode()):016x}\n"
+    (tmp_path / "v1.mlp").write_text(v1)
+    assert L.mgemm_model_load(str(tmp_path / "v1.mlp").encode()) == mg.ERR_MODEL
+    assert "version 2" in mg.last_error()
+    with pytest.raises(ValueError, match="version 2"):
+        learn.parse_model_text(v1)
     (tmp_path / "cut.mlp").write_text(good[: len(good) // 2])
     assert L.mgemm_model_load(str(tmp_path / "cut.mlp").encode()) == mg.ERR_MODEL
     assert L.mgemm_model_load(str(tmp_path / "absent.mlp").encode()) == mg.ERR_MODEL

@@ -1,6 +1,7 @@
 """Host logic of the autotuner and the learned predictor (no GPU): shape sets,
 the resumable JSONL database, the compact database, exhaustive best and regret,
 dataset construction and the single-configuration baseline."""
+import collections
 import json
 import os
 
@@ -86,6 +87,17 @@ def test_compact_roundtrip(tmp_path):
     assert got == want
 
 
+def test_features_flag_whole_16_byte_rows():
+    """The last feature is 1 exactly where the three-stage kernels could load the
+    rows of an unpadded product: n and k multiples of 2 (FP64) or 4 (FP32)."""
+    f = learn.raw_features
+    assert np.allclose(f(100, 66, 64, 0), [np.log2(100), np.log2(66), 6, 1, 0, 1])
+    assert f(100, 65, 64, 0)[5] == 0 and f(100, 66, 63, 0)[5] == 0
+    assert f(100, 66, 64, 1)[5] == 0 and f(7, 68, 60, 1)[5] == 1
+    assert learn.rows_whole_loads(64, 64, 0, lda=65) is False
+    assert learn.rows_whole_loads(64, 64, 1, ldb=66) is False
+
+
 def test_dataset_targets_masks_and_single_best():
     table = [(0, (1,)), (0, (2,)), (1, (1,))]
     recs = []
@@ -101,7 +113,7 @@ def test_dataset_targets_masks_and_single_best():
     assert ds.shapes == shapes[:3]
     assert np.allclose(ds.T, [[0.5, 1.0, 0.0], [1.0, 0.5, 0.0], [0.0, 0.0, 1.0]])
     assert np.array_equal(ds.M, [[1, 1, 0], [1, 1, 0], [0, 0, 1]])
-    assert np.allclose(ds.X[0], [6, 6, 6, 1, 0, 0]) and np.allclose(ds.X[2], [6, 6, 6, 0, 1, 0])
+    assert np.allclose(ds.X[0], [6, 6, 6, 1, 0, 1]) and np.allclose(ds.X[2], [6, 6, 6, 0, 1, 1])
     base = learn.single_best_baseline(ds, table)
     # geometric means of (0.5, 1.0) and (1.0, 0.5) tie: the first slot wins
     assert base[0] == 0 and base[1] == 2
@@ -133,7 +145,12 @@ def test_shipped_database_covers_the_registry():
     dts = {r["dtype"] for r in db.records}
     assert dts == {0, 1}
     n_shapes = len({(r["dtype"], r["m"], r["n"], r["k"]) for r in db.records})
-    assert n_shapes == 8600          # train + held-out + aligned, both dtypes
+    assert n_shapes == 14600         # train, train2, held-out, aligned; both dtypes
+    # every shape measured with every registered configuration of its dtype
+    import paper_1706_10086_amd as mg
+    per = collections.Counter((r["dtype"], r["m"], r["n"], r["k"]) for r in db.records)
+    want = {dt: len(mg.configs(dt)) for dt in (0, 1)}
+    assert all(c == want[key[0]] for key, c in per.items())
 
 
 def test_raw_grid_and_validity_rules():
@@ -217,6 +234,11 @@ def test_aligned_shape_set():
     assert all(x % 4 == 0 and 64 <= x <= 16384 for s in al for x in s)
     assert not set(al) & (set(tune.shape_set("train")) | set(tune.shape_set("heldout")))
     assert tune.shape_set("aligned")[:7] == al[:7]
+    t2 = tune.shape_set("train2")
+    assert len(t2) == 3000 and len(set(t2)) == 3000
+    assert all(64 <= x <= 16384 for s in t2 for x in s)
+    assert not set(t2) & (set(tune.shape_set("train")) | set(tune.shape_set("heldout")) | set(al))
+    assert t2[:3] == [(4124, 1073, 2042), (1103, 4803, 73), (1575, 13872, 3795)]
     with pytest.raises(ValueError):
         tune.shape_set("other")
 
