@@ -6,7 +6,7 @@ default configuration choice (the kernels the sweep and the headline time).
   out); normwise relative error <= 1e-13 and every element within
   gamma_{k+2} (|A||B| + |C|) of the oracle, widened by the oracle's own bound
   (Higham, Sec. 3.5).
-* FP32, N = 4096, the same recipe on float inputs: every element within
+* FP32, N = 1024 and 4096, the same recipe on float inputs: every element within
   gamma_{k+2} with u = 2^-24 of the FP64 oracle on the same float values (plus
   the oracle's own FP64 bound).
 * Emulated FP64 on the wide-range stress inputs (entries u * 2^e, e uniform in
@@ -78,10 +78,10 @@ def test_fp64_square_full_matrix(dev, orc, n):
     assert worst <= 1.0
 
 
-def test_fp32_square_full_matrix(dev, orc):
-    n = 4096
+@pytest.mark.parametrize("n", [1024, 4096])
+def test_fp32_square_full_matrix(dev, orc, n):
     say(f"full matrix fp32 n={n}: inputs")
-    sa, sb, sc = synth.seeds_for(1, 12)
+    sa, sb, sc = synth.seeds_for(1, int(np.log2(n)))
     A, B, C = (synth.uniform_pm1((n, n), s).astype(np.float32) for s in (sa, sb, sc))
     tA, tB, tC = (torch.from_numpy(X).to(dev) for X in (A, B, C))
     mg.gemm(tA, tB, tC, 1.0, 1.0)
