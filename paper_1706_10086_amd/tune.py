@@ -89,7 +89,10 @@ class DB:
     bad_lines: int = 0
 
     @classmethod
-    def load(cls, path: str) -> "DB":
+    def load(cls, path: str, raw: bool = False) -> "DB":
+        """The database at ``path`` (empty if absent); unreadable lines are
+        counted, not fatal.  Refined measurements replace the sweep's unless
+        ``raw`` (every record as written)."""
         recs, bad = [], 0
         if os.path.exists(path):
             with open(path) as f:
@@ -110,7 +113,7 @@ class DB:
                         recs.extend(rs)
                     except (ValueError, KeyError, TypeError):
                         bad += 1
-        return cls(path, prefer_refined(recs), bad)
+        return cls(path, recs if raw else prefer_refined(recs), bad)
 
     def keys(self) -> set:
         return {key_of(r) for r in self.records}
@@ -597,12 +600,56 @@ def tune_batch(As, Bs, Cs, alphas=1.0, betas=0.0, dtype=F64, rules=None, reps=5,
     return out
 
 
+def _parse_cfg(text: str) -> tuple:
+    v = tuple(int(x) for x in text.split(","))
+    if len(v) != 7:
+        raise ValueError(f"a configuration is 7 integers (bm,bn,bk,waves,ept,dbuf,occ): {text}")
+    return v
+
+
+def shapes_with_top(db: DB, dtype: int, shapes, cfgs, top: int) -> list:
+    """The shapes of ``shapes`` on which one of ``cfgs`` is among the ``top``
+    fastest configurations measured in ``db``."""
+    by = {}
+    for r in db.records:
+        if r["dtype"] == dtype:
+            by.setdefault((r["m"], r["n"], r["k"]), {})[tuple(r["cfg"])] = r["median_ms"]
+    out = []
+    for s in shapes:
+        d = by.get(tuple(s), {})
+        best = sorted(d, key=lambda c: d[c])[:top]
+        if any(c in best for c in cfgs):
+            out.append(tuple(s))
+    return out
+
+
+def merge_databases(base_paths, update_paths, out: str) -> DB:
+    """One compact database from sweep and refinement databases (JSONL or compact):
+    the ``update_paths`` hold later measurements (configurations registered since,
+    and refinements of the shapes where one of them ranks among the fastest); their
+    refinement records replace the earlier ones of the same shapes (the later pass
+    re-timed that shape's current fastest configurations together)."""
+    def load(p):
+        d = load_compact(p) if p.endswith(".gz") else DB.load(p, raw=True)
+        if d.bad_lines:
+            raise ValueError(f"{p}: {d.bad_lines} unreadable lines")
+        return d.records
+    base = [r for p in base_paths for r in load(p)]
+    upd = [r for p in update_paths for r in load(p)]
+    again = {(r["device"], r["dtype"], r["m"], r["n"], r["k"]) for r in upd if r.get("refined")}
+    kept = [r for r in base if not (r.get("refined") and
+                                    (r["device"], r["dtype"], r["m"], r["n"], r["k"]) in again)]
+    db = DB(out, prefer_refined(kept + upd), 0)
+    save_compact(db, out)
+    return db
+
+
 def main(argv=None):
     import argparse
     ap = argparse.ArgumentParser(description="autotuner sweep (resumable JSONL database)")
-    ap.add_argument("--set", choices=["train", "heldout", "aligned", "train2"], required=True)
-    ap.add_argument("--dtype", choices=["f64", "f32"], required=True)
-    ap.add_argument("--db", required=True)
+    ap.add_argument("--set", choices=["train", "heldout", "aligned", "train2"])
+    ap.add_argument("--dtype", choices=["f64", "f32"])
+    ap.add_argument("--db")
     ap.add_argument("--count", type=int, default=None)
     ap.add_argument("--reps", type=int, default=2)
     ap.add_argument("--seconds", type=float, default=None,
@@ -612,12 +659,28 @@ def main(argv=None):
                          "shape of the set already in --db (and --from databases)")
     ap.add_argument("--from", dest="sources", action="append", default=[],
                     help="(with --refine) further databases holding the sweep's records "
-                         "(JSONL, or the compact .json.gz form)")
+                         "(JSONL, or the compact .json.gz form); (with --merge) the earlier "
+                         "databases")
+    ap.add_argument("--only", action="append", default=[],
+                    help="bm,bn,bk,waves,ept,dbuf,occ: sweep only these registered "
+                         "configurations (into a database of their own); with --refine, "
+                         "refine only the shapes where one of them is among the N fastest")
     ap.add_argument("--skip", default=None,
                     help="text file of 'dtype m n k' lines: shapes measured elsewhere (for "
                          "sweeps split over several databases)")
+    ap.add_argument("--merge", default=None,
+                    help="write this compact database from the --from databases and the "
+                         "--update ones (whose refinements replace earlier ones of a shape)")
+    ap.add_argument("--update", action="append", default=[])
     a = ap.parse_args(argv)
+    if a.merge:
+        db = merge_databases(a.sources, a.update, a.merge)
+        print(f"tune: {len(db.records)} records -> {a.merge}", flush=True)
+        return
+    if not (a.set and a.dtype and a.db):
+        ap.error("--set, --dtype and --db are required unless --merge is given")
     dt = F64 if a.dtype == "f64" else F32
+    only = [_parse_cfg(t) for t in a.only]
     db = DB.load(a.db)
     if db.bad_lines:
         print(f"tune: skipped {db.bad_lines} unreadable database lines", flush=True)
@@ -626,6 +689,8 @@ def main(argv=None):
         for src in a.sources:
             extra = load_compact(src) if src.endswith(".gz") else DB.load(src)
             db.records = prefer_refined(db.records + extra.records)
+        if only:
+            shapes = shapes_with_top(db, dt, shapes, only, a.refine)
         n = refine(shapes, dt, db, top=a.refine, log=lambda s: print(s, flush=True),
                    seconds=a.seconds)
         print(f"tune: {n} new refinement records in {a.db}", flush=True)
@@ -634,7 +699,13 @@ def main(argv=None):
         with open(a.skip) as f:
             done = {tuple(int(x) for x in line.split()) for line in f if line.strip()}
         shapes = [s for s in shapes if (dt, *s) not in done]
-    n = sweep(shapes, dt, db, reps=a.reps, log=lambda s: print(s, flush=True), seconds=a.seconds)
+    cfgs = None
+    if only:
+        cfgs = [c for c in configs(dt) if c.as_tuple() in only]
+        if len(cfgs) != len(set(only)):
+            ap.error("--only names a configuration this library does not register")
+    n = sweep(shapes, dt, db, cfgs=cfgs, reps=a.reps, log=lambda s: print(s, flush=True),
+              seconds=a.seconds)
     print(f"tune: {n} new shape records in {a.db}", flush=True)
 
 

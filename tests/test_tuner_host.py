@@ -280,3 +280,64 @@ def test_shipped_model_file_matches_the_registry():
     I, H, O = 6, 64, len(pred.table)
     assert pred.params.size == H * I + H + H * H + H + O * H + O
     assert np.all(np.isfinite(pred.params))
+
+
+def _shape_line(dt, m, n, k, cfgs, ms, refine=False, device="dev"):
+    r = {"device": device, "build": "b", "dtype": dt, "m": m, "n": n, "k": k, "reps": len(ms[0]),
+         "cfgs": [list(c) for c in cfgs], "ms": ms, "ts": 1.0}
+    if refine:
+        r["refine"] = True
+    return json.dumps(r) + "\n"
+
+
+def test_top_n_selection_for_added_configurations():
+    """Shapes are refined again only where an added configuration ranks among the
+    N fastest."""
+    A, B, C = (1,) * 7, (2,) * 7, (3,) * 7
+    recs = []
+    for (m, t) in ((64, {A: 1.0, B: 2.0, C: 3.0}), (128, {A: 3.0, B: 1.0, C: 2.0})):
+        for c, v in t.items():
+            r = rec(0, m, 64, 64, c, 1.0)
+            r["median_ms"] = v
+            recs.append(r)
+    db = tune.DB("x", recs)
+    shapes = [(64, 64, 64), (128, 64, 64), (256, 64, 64)]
+    assert tune.shapes_with_top(db, 0, shapes, [C], 2) == [(128, 64, 64)]
+    assert tune.shapes_with_top(db, 0, shapes, [C], 3) == [(64, 64, 64), (128, 64, 64)]
+    assert tune.shapes_with_top(db, 1, shapes, [C], 3) == []
+
+
+def test_merge_lets_later_refinements_replace_earlier_ones(tmp_path):
+    """merge_databases: the update databases' refinement of a shape replaces the
+    base databases' refinement of that shape (both passes timed the shape's fastest
+    configurations; the later one includes the configurations added since), so a
+    configuration the later pass left out falls back to its sweep measurement;
+    shapes the update did not refine keep theirs; added configurations join."""
+    A, B, N = (1,) * 7, (2,) * 7, (9,) * 7
+    base = tmp_path / "base.jsonl"
+    upd = tmp_path / "upd.jsonl"
+    n = 1024
+    f = 2.0 * n ** 3 / 1e9                     # TFLOP/s = f / ms for n^3
+    with open(base, "w") as fh:
+        fh.write(_shape_line(0, n, n, n, [A, B], [[4.0, 4.0], [2.0, 2.0]]))
+        fh.write(_shape_line(0, n, n, n, [A, B], [[3.0] * 5, [1.0] * 5], refine=True))
+        fh.write(_shape_line(0, 2 * n, n, n, [A, B], [[4.0, 4.0], [2.0, 2.0]]))
+        fh.write(_shape_line(0, 2 * n, n, n, [B], [[1.5] * 5], refine=True))
+    with open(upd, "w") as fh:
+        fh.write(_shape_line(0, n, n, n, [N], [[0.5, 0.5]]))
+        fh.write(_shape_line(0, n, n, n, [N, B], [[0.8] * 5, [1.6] * 5], refine=True))
+        fh.write(_shape_line(0, 2 * n, n, n, [N], [[8.0, 8.0]]))
+    out = tmp_path / "m.json.gz"
+    tune.main(["--merge", str(out), "--from", str(base), "--update", str(upd)])
+    db = tune.load_compact(str(out))
+    tf = {(r["m"], tuple(r["cfg"])): r["tflops"] for r in db.records}
+    # n^3: the update refined N and B; A falls back to its sweep (4.0 ms)
+    assert tf[(n, N)] == pytest.approx(f / 0.8, rel=1e-4)
+    assert tf[(n, B)] == pytest.approx(f / 1.6, rel=1e-4)
+    assert tf[(n, A)] == pytest.approx(f / 4.0, rel=1e-4)
+    # 2n x n x n: not refined by the update, so the base refinement of B stays
+    assert tf[(2 * n, B)] == pytest.approx(2 * f / 1.5, rel=1e-4)
+    assert tf[(2 * n, A)] == pytest.approx(2 * f / 4.0, rel=1e-4)
+    assert tf[(2 * n, N)] == pytest.approx(2 * f / 8.0, rel=1e-4)
+    with pytest.raises(SystemExit):
+        tune.main(["--dtype", "f64"])
