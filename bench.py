@@ -585,7 +585,7 @@ def leg_tuner(mg):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
         log("bench.py: only --gpus 1 is supported (the library is single-GPU)")
         return 2
     import torch
