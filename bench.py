@@ -247,7 +247,7 @@ def leg_parity(mg, torch, dev):
             "rel_err": float(np.linalg.norm(got - want) / np.linalg.norm(want))}
 
 
-def leg_sweep(mg, torch, dev, sizes=(1024, 2048, 4096, 8192, 16384)):
+def leg_sweep(mg, torch, dev, sizes=(1024, 2048, 4096, 6144, 8192, 16384)):
     """The square sweep: FP64 and FP32 with the library's default configuration,
     uniform[-1,1) inputs drawn on the device, alpha = beta = 1."""
     log("bench: square sweep, FP64 and FP32")

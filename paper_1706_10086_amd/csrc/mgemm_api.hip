@@ -336,6 +336,52 @@ static int32_t run_splitk(const KernelEntry *e, const GemmArgs &a, int32_t dtype
     });
 }
 
+// Three-stage tiles for rows that are whole 16-byte loads, each with the rate it
+// sustains while every compute unit is busy (TFLOP/s: square N = 12288 on MI355X,
+// calls back to back).  A product of T tiles of one of them runs in
+// R = ceil(T / CUs) rounds that are T / (R CUs) full; the built-in choice takes
+// the tile with the highest rate times fill when that fill is at least
+// WAVE_FILL_MIN (fewer tiles than that: the measured table decides).  On the
+// tuner's shapes with such rows this came 1.1 % (FP64) and 1.4-2.3 % (FP32) closer
+// to the exhaustive best than the preference list and table alone; at N = 6144 FP64
+// it takes the 128 x 128 tile (2304 tiles, 9 full rounds: 70 TFLOP/s) over the
+// 256 x 128 one (1152 tiles, 4.5 rounds: 65).
+struct PipeRate {
+    mgemm_cfg cfg;
+    double tflops;
+};
+static const PipeRate kPipeRatesF64[] = {{{256, 128, 16, 8, 2, 2, 2}, 72.5},
+                                         {{128, 128, 16, 8, 2, 2, 2}, 70.4},
+                                         {{64, 64, 32, 4, 2, 2, 1}, 54.2}};
+static const PipeRate kPipeRatesF32[] = {{{256, 128, 32, 8, 4, 2, 2}, 141.0},
+                                         {{128, 128, 32, 8, 4, 2, 2}, 135.1},
+                                         {{64, 64, 32, 4, 4, 2, 1}, 120.6}};
+constexpr double WAVE_FILL_MIN = 0.8;
+
+static const KernelEntry *wave_filled_pipe(const GemmArgs &a, int32_t dtype) {
+    const int cus = compute_units();
+    if (cus <= 0) return nullptr;
+    const PipeRate *pr = dtype == MGEMM_F32 ? kPipeRatesF32 : kPipeRatesF64;
+    constexpr int NP = 3;
+    int best = -1;
+    double score = 0.0, fill_best = 0.0;
+    for (int i = 0; i < NP; ++i) {
+        const int64_t t = tiles_of(a.m, a.n, pr[i].cfg);
+        if (t <= 0) continue;
+        const int64_t rounds = (t + cus - 1) / cus;
+        const double fill = (double)t / (double)(rounds * cus);
+        if (pr[i].tflops * fill > score) {
+            score = pr[i].tflops * fill;
+            fill_best = fill;
+            best = i;
+        }
+    }
+    if (best < 0 || fill_best < WAVE_FILL_MIN) return nullptr;
+    int cnt = 0;
+    const KernelEntry *reg = registry(dtype, &cnt);
+    return find_entry(reg, cnt, pr[best].cfg);
+}
+
 // What gemm_ex runs for one FP64 or FP32 product (CallPlan, mgemm_internal.h).
 // A loaded cost model is evaluated on the device only when model_may_launch
 // (else only its cached choices are used).
@@ -352,26 +398,35 @@ int32_t plan_call(const GemmArgs &a, int32_t dtype, const mgemm_cfg *cfg,
         // learned), and inside it for long k
         cp.sp = splitk_plan(a, e, dtype);
     }
-    if (!cfg && in_range && cp.sp.S == 1) {
-        // a loaded cost model's choice (evaluated on the device once per shape)
-        mgemm_cfg mc;
-        const KernelEntry *me = nullptr;
-        if (model_choose(dtype, a.m, a.n, a.k, rows_whole_loads(a, dtype), model_may_launch,
-                         &mc) == 0) {
-            int cnt = 0;
-            const KernelEntry *reg = registry(dtype, &cnt);
-            me = find_entry(reg, cnt, mc);
+    if (!cfg && cp.sp.S == 1) {
+        const bool rows16 = rows_whole_loads(a, dtype);
+        if (in_range) {
+            // a loaded cost model's choice (evaluated on the device once per shape)
+            mgemm_cfg mc;
+            const KernelEntry *me = nullptr;
+            if (model_choose(dtype, a.m, a.n, a.k, rows16, model_may_launch, &mc) == 0) {
+                int cnt = 0;
+                const KernelEntry *reg = registry(dtype, &cnt);
+                me = find_entry(reg, cnt, mc);
+            }
+            g_err.clear();     // a model that could not be used leaves the built-in choice
+            if (me) {
+                cp.e = me;
+                return 0;
+            }
         }
-        g_err.clear();     // a model that could not be used leaves the built-in choice
-        if (me) {
-            cp.e = me;
-            return 0;
+        // rows the three-stage kernels load: the three-stage tile that fills the
+        // compute units' rounds best, where one fills them well enough
+        if (rows16) {
+            if (const KernelEntry *q = wave_filled_pipe(a, dtype)) {
+                cp.e = q;
+                return 0;
+            }
         }
         // the configuration measured fastest for shapes like this one: always for
         // rows the three-stage kernels cannot load (which the preference list
         // favours), else where the list names a two-stage configuration
-        const bool rows16 = rows_whole_loads(a, dtype);
-        if (!rows16 || e->cfg.double_buffer != 2) {
+        if (in_range && (!rows16 || e->cfg.double_buffer != 2)) {
             const KernelEntry *t = measured_entry(dtype, rows16, a.m, a.n, a.k);
             if (t) e = t;
         }
