@@ -110,13 +110,16 @@ MGEMM_API int32_t gemm(int64_t m, int64_t n, int64_t k, double alpha,
  *
  * The library's choice (MGEMM_F64, MGEMM_F32): the largest preferred tile that
  * still gives enough work-groups for the m x n output; split-k below where k >=
- * 2048 or m, n or k lies outside [64, 16384]; otherwise (with m, n, k in
- * [64, 16384]), for rows the three-stage kernels cannot load (n, lda, ldb not
- * multiples of 16 bytes, or A, B not 16-byte aligned), or where the preferred
- * tile is a two-stage one, the configuration measured fastest on the tuner's
- * shapes of the same row class in and around the (floor(log2 m), floor(log2 n),
- * floor(log2 k)) cell.  With a cost model loaded (mgemm_model_load), its
- * prediction replaces that last step and the preferred tile.
+ * 2048 or m, n or k lies outside [64, 16384]; otherwise, with a cost model loaded
+ * (mgemm_model_load) and m, n, k in [64, 16384], its prediction; else, for rows
+ * the three-stage kernels can load (n, lda, ldb multiples of 16 bytes, A and B
+ * 16-byte aligned), the three-stage tile (256 x 128, 128 x 128 or 64 x 64) whose
+ * sustained rate times the fill of its rounds of one work-group per compute unit
+ * is highest, if that fill is at least 80 %; else (m, n, k in [64, 16384]), for
+ * rows the three-stage kernels cannot load or where the preferred tile is a
+ * two-stage one, the configuration measured fastest on the tuner's shapes of the
+ * same row class in and around the (floor(log2 m), floor(log2 n), floor(log2 k))
+ * cell.
  *
  * Split-k (MGEMM_F64 and MGEMM_F32, cfg == NULL only, k >= 2048 or outside the
  * measured range): when the preferred tile leaves fewer than about four
