@@ -33,7 +33,7 @@ EXPORTED = [
     "mgemm_config_get", "mgemm_release_workspace", "mgemm_probe_mfma", "mgemm_probe_mfma_raw",
     "gemm_batched", "gemm_batched_plan_create", "gemm_batched_plan_execute",
     "gemm_batched_plan_destroy", "gemm_batched_plan_info", "mgemm_host_alloc", "mgemm_host_free",
-    "mgemm_config_flags", "gemm_ex_noalloc",
+    "mgemm_config_flags", "gemm_ex_noalloc", "mgemm_choice",
 ]
 CFG_GEMM, CFG_BATCHED, CFG_SPLITK = 1, 2, 4
 
@@ -99,6 +99,9 @@ def lib():
     L.mgemm_config_get.restype = i32
     L.mgemm_config_flags.argtypes = [i32, i32]
     L.mgemm_config_flags.restype = i32
+    L.mgemm_choice.argtypes = [i64, i64, i64, i64, i64, i32, ctypes.POINTER(Cfg),
+                               ctypes.POINTER(i32)]
+    L.mgemm_choice.restype = i32
     L.mgemm_release_workspace.argtypes = []
     L.mgemm_release_workspace.restype = i32
     L.mgemm_probe_mfma.argtypes = [i32, p, p, p, p]
@@ -188,6 +191,17 @@ class HostBuffer:
             self.free()
         except Exception:
             pass
+
+
+def choice(m: int, n: int, k: int, dtype: int = F64, lda: int | None = None,
+           ldb: int | None = None) -> tuple[Cfg, int]:
+    """(configuration, k ranges) that gemm with no configuration runs for an
+    m x n x k product with aligned operands (mgemm_choice)."""
+    c = Cfg()
+    s = ctypes.c_int32()
+    _check(lib().mgemm_choice(m, n, k, k if lda is None else lda, n if ldb is None else ldb,
+                              dtype, ctypes.byref(c), ctypes.byref(s)))
+    return c, int(s.value)
 
 
 def configs(dtype: int, need: int = 0) -> list[Cfg]:

@@ -532,6 +532,39 @@ int32_t mgemm_config_flags(int32_t dtype, int32_t i) {
     return f;
 }
 
+int32_t mgemm_choice(int64_t m, int64_t n, int64_t k, int64_t lda, int64_t ldb, int32_t dtype,
+                     mgemm_cfg *out, int32_t *splits) {
+    g_err.clear();
+    if (m < 1) return set_error(-1, "m < 1");
+    if (n < 1) return set_error(-2, "n < 1");
+    if (k < 1) return set_error(-3, "k < 1");
+    if (lda < k) return set_error(-4, "lda < k");
+    if (ldb < n) return set_error(-5, "ldb < n");
+    if (dtype != MGEMM_F64 && dtype != MGEMM_F32)
+        return set_error(-6, "dtype must be MGEMM_F64 or MGEMM_F32");
+    if (!out) return set_error(-7, "out is NULL");
+    if (!splits) return set_error(-8, "splits is NULL");
+    // stand-in operands: 16-byte aligned addresses that are never dereferenced
+    void *const base = (void *)(uintptr_t)256;
+    GemmArgs a{m, n, k, 1.0, 0.0, base, lda, base, ldb, base, n};
+    CallPlan cp;
+    const int32_t rc = plan_call(a, dtype, nullptr, false, cp);
+    if (rc) return rc;
+    *splits = cp.sp.S;
+    *out = cp.e->cfg;
+    if (cp.sp.S > 1 && cp.sp.pipe) {
+        // the three-stage 128 x 128 tile runs the ranges
+        int cnt = 0;
+        const KernelEntry *reg = registry(dtype, &cnt);
+        for (int i = 0; i < cnt; ++i)
+            if (reg[i].cfg.bm == 128 && reg[i].cfg.bn == 128 && reg[i].cfg.double_buffer == 2) {
+                *out = reg[i].cfg;
+                break;
+            }
+    }
+    return 0;
+}
+
 int32_t mgemm_config_get(int32_t dtype, int32_t i, mgemm_cfg *out) {
     if (dtype < MGEMM_F64 || dtype > MGEMM_CRT_INT8) return -1;
     int cnt = 0;

@@ -119,6 +119,18 @@ def test_config_registry(L):
     assert L.mgemm_config_get(mg.F64, 10 ** 6, ctypes.byref(c)) == -2
 
 
+def test_choice_argument_errors(L):
+    """mgemm_choice checks its arguments before asking the device anything."""
+    c, s = mg.Cfg(), ctypes.c_int32()
+    cases = [((0, 4, 4, 4, 4, mg.F64), -1), ((4, 0, 4, 4, 4, mg.F64), -2),
+             ((4, 4, 0, 4, 4, mg.F64), -3), ((4, 4, 8, 7, 4, mg.F64), -4),
+             ((4, 8, 4, 4, 7, mg.F64), -5), ((4, 4, 4, 4, 4, mg.SPLIT_BF16), -6)]
+    for args, code in cases:
+        assert L.mgemm_choice(*args, ctypes.byref(c), ctypes.byref(s)) == code, args
+    assert L.mgemm_choice(4, 4, 4, 4, 4, mg.F64, None, ctypes.byref(s)) == -7
+    assert L.mgemm_choice(4, 4, 4, 4, 4, mg.F64, ctypes.byref(c), None) == -8
+
+
 def test_host_alloc_argument_errors(L):
     # both are rejected before any HIP call
     h, d = ctypes.c_void_p(), ctypes.c_void_p()

@@ -152,3 +152,40 @@ def test_builtin_choice_runs_the_measured_configuration():
             u = 2.0 ** -24 if dt == mg.F32 else 2.0 ** -53
             bound = (k + 2) * u / (1 - (k + 2) * u) * (np.abs(A[rows]) @ np.abs(B))
             assert np.all(np.abs(got - ref) <= bound), (m, n, k)
+
+
+def test_choice_c_abi_matches_the_rule():
+    """mgemm_choice (what gemm with no configuration runs, for aligned operands)
+    agrees with the rule written out in tests/choice_rule.py wherever k is not cut:
+    the round-fill rule for rows of whole 16-byte loads, the preference list and
+    the measured table otherwise; squares, held-out and aligned shapes, both
+    dtypes."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1706_10086_amd.csrc import gen_choice_table as gen
+    import choice_rule as host
+    mg.model_load(None)
+    db = tune.load_compact(DB_PATH)
+    tables = gen.build_tables(db.records, gen.training_shapes())
+    shapes = [(n, n, n) for n in (512, 1024, 1536, 2048, 2560, 3072, 4096, 5120, 6144, 8192)]
+    shapes += tune.shape_set("heldout")[:150] + tune.shape_set("aligned")[:100]
+    checked = 0
+    for dt in (mg.F64, mg.F32):
+        for (m, n, k) in shapes:
+            cfg, splits = mg.choice(m, n, k, dt)
+            if splits > 1:
+                continue
+            assert cfg.as_tuple() == host.library_choice(tables, dt, m, n, k), (dt, m, n, k)
+            checked += 1
+    print(f"  {checked} choices agree", flush=True)
+    assert checked >= 400
+    # the round-fill rule on FP64 squares
+    assert mg.choice(1024, 1024, 1024)[0].as_tuple()[:2] == (64, 64)
+    assert mg.choice(6144, 6144, 6144)[0].as_tuple()[:2] == (128, 128)
+    assert mg.choice(8192, 8192, 8192)[0].as_tuple()[:2] == (256, 128)
+    # an odd leading dimension of A breaks the 16-byte rows: the measured table's
+    # cell for that row class decides (the rule's row class follows lda, here k + 1)
+    c_odd, s_odd = mg.choice(6144, 6144, 6144, lda=6145)
+    assert s_odd == 1
+    assert c_odd.as_tuple() == host.library_choice(tables, mg.F64, 6144, 6144, 6145)
+    assert c_odd.double_buffer != 2
