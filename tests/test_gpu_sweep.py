@@ -74,3 +74,43 @@ def test_sweep_resumes_and_finds_a_reproducible_best(dt, tmp_path):
         u = 2.0 ** -24 if dt == mg.F32 else 2.0 ** -53
         bound = (k + 2) * u / (1 - (k + 2) * u) * (np.abs(A[rows]) @ np.abs(B))
         assert np.all(np.abs(got - ref) <= bound)
+
+
+def test_added_configurations_sweep_refine_and_merge(tmp_path):
+    """The path that brings configurations registered later into a database, with
+    the tuner's command line: a sweep of those configurations alone (one shape
+    record each, nothing else timed), a refinement of only the shapes where one of
+    them ranks among the 4 fastest, and the merge, after which every shape has every
+    configuration and the refined medians of the later pass."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    dt = mg.F64
+    base = str(tmp_path / "base.jsonl")
+    shapes = tune.shape_set("aligned", count=3)
+    allc = mg.configs(dt)
+    added = [c for c in allc if (c.bm, c.bn, c.double_buffer) == (64, 64, 2)]
+    assert added
+    older = [c for c in allc if c.as_tuple() not in {a.as_tuple() for a in added}]
+    # the earlier database: every other configuration swept
+    assert tune.sweep(shapes, dt, tune.DB.load(base), cfgs=older, reps=2) == len(shapes)
+    new = str(tmp_path / "new.jsonl")
+    only = [",".join(str(v) for v in a.as_tuple()) for a in added]
+    args = ["--set", "aligned", "--count", "3", "--dtype", "f64", "--db", new]
+    tune.main(args + sum((["--only", o] for o in only), []))
+    d = tune.DB.load(new)
+    assert {tuple(r["cfg"]) for r in d.records} == {a.as_tuple() for a in added}
+    assert len({(r["m"], r["n"], r["k"]) for r in d.records}) == len(shapes)
+    # refine where an added configuration is among the 4 fastest
+    comb = tune.DB("x", tune.prefer_refined(tune.DB.load(base).records + d.records))
+    want = tune.shapes_with_top(comb, dt, shapes, [a.as_tuple() for a in added], 4)
+    tune.main(args + ["--refine", "4", "--from", base] + sum((["--only", o] for o in only), []))
+    refined = {(r["m"], r["n"], r["k"]) for r in tune.DB.load(new).records if r["refined"]}
+    assert refined == set(want)
+    out = str(tmp_path / "m.json.gz")
+    tune.main(["--merge", out, "--from", base, "--update", new])
+    m = tune.load_compact(out)
+    per = {}
+    for r in m.records:
+        per.setdefault((r["m"], r["n"], r["k"]), set()).add(tuple(r["cfg"]))
+    assert set(per) == set(shapes)
+    assert all(v == {c.as_tuple() for c in allc} for v in per.values())
