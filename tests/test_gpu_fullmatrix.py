@@ -9,6 +9,8 @@ default configuration choice (the kernels the sweep and the headline time).
 * FP32, N = 1024 and 4096, the same recipe on float inputs: every element within
   gamma_{k+2} with u = 2^-24 of the FP64 oracle on the same float values (plus
   the oracle's own FP64 bound).
+* Squares whose tile the round-fill rule picks (FP64 N = 3072, every element; FP64
+  and FP32 N = 6144, 256 rows), within the same gamma_{k+2} bounds.
 * Emulated FP64 on the wide-range stress inputs (entries u * 2^e, e uniform in
   [-20, 20]): at N = 4096 every element, at N = 8192 256 sampled rows, against
   the double-double (Dot2) oracle, normwise <= 1e-14 for every emulation, and
@@ -135,3 +137,36 @@ def test_stress_inputs_against_both_oracles(dev, stress, dtype, n):
         f"FP64 oracle vs Dot2 {nrm(f64, d2):.3e}")
     assert e2 <= (1e-13 if dtype == mg.F64 else 1e-14)
     assert e64 <= 1e-13
+
+
+@pytest.mark.parametrize("dtype,n", [(mg.F64, 3072), (mg.F64, 6144), (mg.F32, 6144)])
+def test_round_fill_squares(dev, orc, dtype, n):
+    """Squares whose tile the round-fill rule picks (N = 3072: 64 x 64, 6144: 128 x
+    128): at N = 3072 every element, at 6144 256 rows spread over the matrix,
+    within gamma_{k+2}(|A||B| + |C|) of the FP64 oracle (plus the oracle's own
+    bound), FP64 also normwise <= 1e-13."""
+    cfg, splits = mg.choice(n, n, n, dtype)
+    assert splits == 1 and cfg.double_buffer == 2
+    say(f"round-fill square {mg.DTYPE_NAMES[dtype]} n={n}: {cfg}")
+    sa, sb, sc = synth.seeds_for(3, int(np.log2(n)) + (dtype == mg.F32))
+    A, B, C = (synth.uniform_pm1((n, n), s) for s in (sa, sb, sc))
+    tdt = torch.float64
+    if dtype == mg.F32:
+        A, B, C = (x.astype(np.float32).astype(np.float64) for x in (A, B, C))
+        tdt = torch.float32
+    tA, tB, tC = (torch.from_numpy(X).to(dev, tdt) for X in (A, B, C))
+    mg.gemm(tA, tB, tC, 1.0, 1.0, dtype=dtype)
+    torch.cuda.synchronize()
+    rows = np.arange(n) if n <= 4096 else np.linspace(0, n - 1, 256).astype(np.int64)
+    got = tC[torch.from_numpy(rows).to(dev)].cpu().double().numpy()
+    del tA, tB, tC
+    ref = orc.gemm_f64(1.0, A[rows], B, 1.0, C[rows], nthreads=orc.num_procs())
+    mag = np.abs(A[rows]) @ np.abs(B)
+    mag += np.abs(C[rows])
+    u = 2.0 ** -24 if dtype == mg.F32 else 2.0 ** -53
+    bound = (gamma(n + 2, u) + gamma(n + 2, 2.0 ** -53)) * mag
+    worst = float(np.max(np.abs(got - ref) / bound))
+    say(f"  {len(rows)} rows: worst element / bound {worst:.3e}, normwise {nrm(got, ref):.3e}")
+    assert worst <= 1.0
+    if dtype == mg.F64:
+        assert nrm(got, ref) <= 1e-13
