@@ -48,7 +48,7 @@ PEAK_INT8_TOPS = 5033.2
 # Measured HBM traffic of the N = 8192 FP64 launch (FETCH_SIZE x 2.0 + WRITE_SIZE x
 # 1.0, the factors a plain copy of known size gives); valid for the kernel as
 # profiled -- to be re-measured whenever the FP64 tile kernel changes.
-TRAFFIC_F64_N8192 = 21.22e9
+TRAFFIC_F64_N8192 = 22.05e9
 
 
 def parse():
@@ -65,6 +65,9 @@ def parse():
                     default=None,
                     help="run only this extra leg and print its JSON (for profiling runs; "
                          "'copy' is the calibration workload of the traffic counters)")
+    ap.add_argument("--cfg", default=None,
+                    help="bm,bn,bk,waves,ept,dbuf,occ: time this registered configuration "
+                         "instead of the library's choice (profiling runs)")
     ap.add_argument("--copy-mib", type=int, default=1024, help="copy leg: MiB per copy")
     ap.add_argument("--copy-reps", type=int, default=3, help="copy leg: number of copies")
     return ap.parse_args()
@@ -95,6 +98,18 @@ def leg_copy(torch, dev, mib=1024, reps=3):
         dst.copy_(src)
     torch.cuda.synchronize()
     return {"bytes_per_copy": 8 * n, "copies": reps}
+
+
+def kernel_name(c: dict) -> str:
+    """The FP64 kernel a registered configuration runs on aligned rows (as the
+    profiler names it)."""
+    wgm = 4 if c["waves"] == 8 and c["bm"] >= c["bn"] else 2
+    wgn = c["waves"] // wgm
+    if c["double_buffer"] == 2:
+        return f"gemm_pipe_kernel<double,{c['bm']},{c['bn']},{c['bk']},{wgm},{wgn}>"
+    return (f"gemm_tiled_kernel<double,{c['bm']},{c['bn']},{c['bk']},...> "
+            f"({c['waves']} waves, {c['elems_per_thread']} per thread, "
+            f"{c['double_buffer'] + 1} stage(s), occupancy {c['occupancy']})")
 
 
 def log(msg):
@@ -610,6 +625,13 @@ def main():
                 "copy": lambda: leg_copy(torch, dev, args.copy_mib, args.copy_reps)}
         print(json.dumps({args.leg: legs[args.leg]()}), flush=True)
         return 0
+    cfg = None
+    if args.cfg:
+        want = tuple(int(x) for x in args.cfg.split(","))
+        cfg = next((c for c in mg.configs(mg.F64) if c.as_tuple() == want), None)
+        if cfg is None:
+            log(f"bench.py: {args.cfg} is not a registered FP64 configuration")
+            return 2
     log(f"bench: generating N={n} inputs")
     sa, sb, sc = synth.seeds_for(1, int(np.log2(n)))
     A = synth.uniform_pm1((n, n), sa)
@@ -621,7 +643,7 @@ def main():
     stream = torch.cuda.current_stream()
 
     def step():
-        mg.gemm(tA, tB, tC, 1.0, 1.0, stream=stream)
+        mg.gemm(tA, tB, tC, 1.0, 1.0, cfg=cfg, stream=stream)
 
     log(f"bench: warmup {args.warmup}")
     for _ in range(args.warmup):
@@ -665,10 +687,7 @@ def main():
         cpu = cpu_baseline(n, A, B, C0, args.cpu_seconds)
     del tA, tB, tC
 
-    cfg_used = None
-    for c in mg.configs(mg.F64):
-        if (c.bm, c.bn, c.bk, c.waves, c.double_buffer) == (256, 128, 16, 8, 2):
-            cfg_used = c.as_dict()
+    cfg_used = (cfg if cfg is not None else mg.choice(n, n, n, mg.F64)[0]).as_dict()
     out = {
         "metric": METRIC,
         "value": round(tflops, 3),
@@ -683,7 +702,9 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"square DGEMM N={n}, FP64 row-major, A,B,C uniform[-1,1], "
-                               f"alpha=1, beta=1 (library's default tile configuration)",
+                               f"alpha=1, beta=1 ("
+                               f"{'explicit' if cfg is not None else 'library' + chr(39) + 's default'}"
+                               f" tile configuration)",
                    "n": n, "alpha": 1.0, "beta": 1.0, "tile_config": cfg_used,
                    "parallelism": "single GPU"},
         "pct_peak": round(100.0 * tflops / PEAK_F64_TFLOPS, 2),
@@ -697,15 +718,15 @@ def main():
                      "frac": round(flops / (kern_ms * 1e-3) / 1e12 / PEAK_F64_TFLOPS, 4),
                      # HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE runs in
                      # profiles/gemm_pipe_f64_N8192_traffic.md (copy-calibrated)
-                     "traffic": TRAFFIC_F64_N8192 if n == 8192 else None,
+                     "traffic": TRAFFIC_F64_N8192 if n == 8192 and cfg is None else None,
                      "traffic_unit": "bytes per launch",
-                     "kernel": "gemm_pipe_kernel<double,256,128,16,4,2> "
-                               "(one launch per step)",
+                     "kernel": kernel_name(cfg_used) + " (one launch per step)",
                      "kernel_avg_ms": round(kern_ms, 4),
                      "work_per_launch": f"2*N^3 = {flops:.4g} FLOP",
                      # Eq. 6 for the kernel's 256 x 128 tiles: the bytes with no cache
                      # reuse, against the algorithmic minimum (A, B, C read, C written)
-                     "traffic_model": {"tiles_no_reuse": pm.tile_traffic_bytes(n, n, n, 256, 128, 8),
+                     "traffic_model": {"tiles_no_reuse": pm.tile_traffic_bytes(
+                                           n, n, n, cfg_used["bm"], cfg_used["bn"], 8),
                                        "algorithmic": 4.0 * 8 * n * n}},
         "cpu_baseline": cpu,
     }
