@@ -348,13 +348,17 @@ MGEMM_API int32_t mgemm_config_flags(int32_t dtype, int32_t i);
  * dimensions lda and ldb, on the current device (its compute units enter the
  * choice); a loaded model enters only through the choices it has cached.  *splits
  * receives the number of k ranges (1: k is not cut; above 1 the ranges run the
- * configuration written to *out).  For callers that want to know, or to record,
+ * configuration written to *out), *main_rows (main_rows may be NULL) the rows
+ * [0, main_rows) that run whole: m without a split, 0 when every row's k is cut,
+ * and in between for a split tail (the rows that fill whole rounds of the compute
+ * units run whole, the remaining rows with k cut).  For callers that want to know, or to record,
  * what the built-in choice does (the paper fixes its tile parameters per device,
  * Sec. 3, Tab. 4; here they are chosen per product).  Returns 0; -1..-3 (m, n or
  * k below 1), -4 (lda < k), -5 (ldb < n), -6 (dtype), -7 / -8 (out / splits NULL);
  * MGEMM_ERR_NOCONFIG if no configuration is registered. */
 MGEMM_API int32_t mgemm_choice(int64_t m, int64_t n, int64_t k, int64_t lda, int64_t ldb,
-                               int32_t dtype, mgemm_cfg *out, int32_t *splits);
+                               int32_t dtype, mgemm_cfg *out, int32_t *splits,
+                               int64_t *main_rows);
 
 /* Frees the library-owned workspace of the current device (split dtypes and
  * split-k) once the work that last used it has finished; 0 on success,

@@ -100,7 +100,7 @@ def lib():
     L.mgemm_config_flags.argtypes = [i32, i32]
     L.mgemm_config_flags.restype = i32
     L.mgemm_choice.argtypes = [i64, i64, i64, i64, i64, i32, ctypes.POINTER(Cfg),
-                               ctypes.POINTER(i32)]
+                               ctypes.POINTER(i32), ctypes.POINTER(i64)]
     L.mgemm_choice.restype = i32
     L.mgemm_release_workspace.argtypes = []
     L.mgemm_release_workspace.restype = i32
@@ -194,14 +194,16 @@ class HostBuffer:
 
 
 def choice(m: int, n: int, k: int, dtype: int = F64, lda: int | None = None,
-           ldb: int | None = None) -> tuple[Cfg, int]:
+           ldb: int | None = None, rows: bool = False):
     """(configuration, k ranges) that gemm with no configuration runs for an
-    m x n x k product with aligned operands (mgemm_choice)."""
+    m x n x k product with aligned operands (mgemm_choice); with rows, also the
+    rows that run whole (m, 0, or the rows before a split tail)."""
     c = Cfg()
     s = ctypes.c_int32()
+    r = ctypes.c_int64()
     _check(lib().mgemm_choice(m, n, k, k if lda is None else lda, n if ldb is None else ldb,
-                              dtype, ctypes.byref(c), ctypes.byref(s)))
-    return c, int(s.value)
+                              dtype, ctypes.byref(c), ctypes.byref(s), ctypes.byref(r)))
+    return (c, int(s.value), int(r.value)) if rows else (c, int(s.value))
 
 
 def configs(dtype: int, need: int = 0) -> list[Cfg]:

@@ -358,7 +358,9 @@ static const PipeRate kPipeRatesF32[] = {{{256, 128, 32, 8, 4, 2, 2}, 141.0},
                                          {{64, 64, 32, 4, 4, 2, 1}, 120.6}};
 constexpr double WAVE_FILL_MIN = 0.8;
 
-static const KernelEntry *wave_filled_pipe(const GemmArgs &a, int32_t dtype) {
+// best_tf: the highest rate x fill among the tiles (0 without a device).
+static const KernelEntry *wave_filled_pipe(const GemmArgs &a, int32_t dtype, double *best_tf) {
+    *best_tf = 0.0;
     const int cus = compute_units();
     if (cus <= 0) return nullptr;
     const PipeRate *pr = dtype == MGEMM_F32 ? kPipeRatesF32 : kPipeRatesF64;
@@ -376,10 +378,58 @@ static const KernelEntry *wave_filled_pipe(const GemmArgs &a, int32_t dtype) {
             best = i;
         }
     }
+    *best_tf = score;
     if (best < 0 || fill_best < WAVE_FILL_MIN) return nullptr;
     int cnt = 0;
     const KernelEntry *reg = registry(dtype, &cnt);
     return find_entry(reg, cnt, pr[best].cfg);
+}
+
+// A split tail: where whole rounds of 128 x 128 tiles leave a last round of few
+// tiles, the tile rows that fill whole rounds run whole and the remaining rows run
+// with k cut into S ranges (S x their tiles <= CUs), so that the last round takes
+// about 1/S of a round plus the sum of the S partial planes.  Taken when the
+// estimate -- the main part at the tile's rate x its fill, the tail at
+// TAIL_RATE_FACTOR of that rate x its fill (shorter k-loops), the sum at
+// SUM_BYTES_PER_S -- beats plain_tf, the best single-tile estimate, by TAIL_GAIN.
+// (N = 3072 FP64: 21 of 24 tile rows whole in two full rounds, 3 rows in 3 ranges
+// of 1024: 53 -> 65 TFLOP/s.)
+constexpr double TAIL_RATE_FACTOR = 0.8;
+constexpr double SUM_BYTES_PER_S = 4e12;
+constexpr double TAIL_GAIN = 1.05;
+
+static bool split_tail_plan(const GemmArgs &a, int32_t dtype, double plain_tf, CallPlan &cp) {
+    const int cus = compute_units();
+    if (cus <= 0 || !pipe_splitk_eligible(a, dtype)) return false;
+    const PipeRate &p = (dtype == MGEMM_F32 ? kPipeRatesF32 : kPipeRatesF64)[1];   // 128 x 128
+    const int64_t tm = (a.m + 127) / 128, tn = (a.n + 127) / 128;
+    const int64_t full = tm * tn / cus;                  // whole rounds
+    if (full < 1) return false;
+    const int64_t r1 = full * cus / tn;                  // tile rows run whole
+    if (r1 < 1 || r1 >= tm) return false;
+    const int64_t t1 = r1 * tn, t2 = (tm - r1) * tn;
+    SplitPlan sp;
+    cut_k(a.k, cus / t2, sp);
+    if (sp.S < 2) return false;
+    const int64_t main_rows = r1 * 128;
+    const double w = 2.0 * (double)a.m * (double)a.n * (double)a.k * 1e-12;   // TFLOP
+    const double wm = w * (double)main_rows / (double)a.m;
+    const double fill_m = (double)t1 / (double)(((t1 + cus - 1) / cus) * cus);
+    const double fill_t = std::min(1.0, (double)(t2 * sp.S) / (double)cus);
+    const double sum_s = (double)(sp.S + 2) * (double)(a.m - main_rows) * (double)a.n *
+                         (double)elem_size(dtype) / SUM_BYTES_PER_S;
+    const double t = wm / (p.tflops * fill_m) + (w - wm) / (p.tflops * TAIL_RATE_FACTOR * fill_t) +
+                     sum_s;
+    if (w / t < TAIL_GAIN * plain_tf) return false;
+    int cnt = 0;
+    const KernelEntry *reg = registry(dtype, &cnt);
+    const KernelEntry *e = find_entry(reg, cnt, p.cfg);
+    if (!e) return false;
+    sp.pipe = true;
+    cp.e = e;
+    cp.sp = sp;
+    cp.main_rows = main_rows;
+    return true;
 }
 
 // What gemm_ex runs for one FP64 or FP32 product (CallPlan, mgemm_internal.h).
@@ -415,10 +465,14 @@ int32_t plan_call(const GemmArgs &a, int32_t dtype, const mgemm_cfg *cfg,
                 return 0;
             }
         }
-        // rows the three-stage kernels load: the three-stage tile that fills the
-        // compute units' rounds best, where one fills them well enough
+        // rows the three-stage kernels load: a split tail where it pays, else the
+        // three-stage tile that fills the compute units' rounds best, where one
+        // fills them well enough
         if (rows16) {
-            if (const KernelEntry *q = wave_filled_pipe(a, dtype)) {
+            double best_tf = 0.0;
+            const KernelEntry *q = wave_filled_pipe(a, dtype, &best_tf);
+            if (split_tail_plan(a, dtype, best_tf, cp)) return 0;
+            if (q) {
                 cp.e = q;
                 return 0;
             }
@@ -456,6 +510,14 @@ static int32_t gemm_impl(int64_t m, int64_t n, int64_t k, double alpha, const vo
     CallPlan cp;
     rc = plan_call(a, dtype, cfg, !capturing(s) && !capturing(g_stream), cp);
     if (rc) return rc;
+    if (cp.main_rows > 0) {
+        GemmArgs am = a;
+        am.m = cp.main_rows;
+        hipError_t he = (cp.al ? cp.e->launch : cp.e->launch_unaligned)(am, s);
+        if (he != hipSuccess) return hip_error(he, "gemm launch");
+        return run_splitk(cp.e, rows_from(a, cp.main_rows, elem_size(dtype)), dtype, cp.al, cp.sp,
+                          s);
+    }
     if (cp.sp.S > 1) return run_splitk(cp.e, a, dtype, cp.al, cp.sp, s);
     hipError_t he = (cp.al ? cp.e->launch : cp.e->launch_unaligned)(a, s);
     if (he != hipSuccess) return hip_error(he, "gemm launch");
@@ -533,7 +595,7 @@ int32_t mgemm_config_flags(int32_t dtype, int32_t i) {
 }
 
 int32_t mgemm_choice(int64_t m, int64_t n, int64_t k, int64_t lda, int64_t ldb, int32_t dtype,
-                     mgemm_cfg *out, int32_t *splits) {
+                     mgemm_cfg *out, int32_t *splits, int64_t *main_rows) {
     g_err.clear();
     if (m < 1) return set_error(-1, "m < 1");
     if (n < 1) return set_error(-2, "n < 1");
@@ -552,6 +614,7 @@ int32_t mgemm_choice(int64_t m, int64_t n, int64_t k, int64_t lda, int64_t ldb, 
     if (rc) return rc;
     *splits = cp.sp.S;
     *out = cp.e->cfg;
+    if (main_rows) *main_rows = cp.main_rows > 0 ? cp.main_rows : (cp.sp.S > 1 ? 0 : m);
     if (cp.sp.S > 1 && cp.sp.pipe) {
         // the three-stage 128 x 128 tile runs the ranges
         int cnt = 0;

@@ -137,11 +137,24 @@ struct SplitPlan {
 
 // What gemm_ex runs for one FP64 or FP32 product: the kernel entry, whether A
 // and B rows take vector loads (al), and for the built-in choice the split of k.
+// With main_rows > 0, rows [0, main_rows) run whole on e and only the remaining
+// rows run the split (a tail that would otherwise leave most compute units idle
+// in a last round).
 struct CallPlan {
     const KernelEntry *e = nullptr;
     bool al = false;
     SplitPlan sp;
+    int64_t main_rows = 0;
 };
+
+// Rows [r, m) of a product: A and C start r rows further on.
+inline GemmArgs rows_from(const GemmArgs &a, int64_t r, size_t es) {
+    GemmArgs t = a;
+    t.m = a.m - r;
+    t.A = (const char *)a.A + (size_t)(r * a.lda) * es;
+    t.C = (char *)a.C + (size_t)(r * a.ldc) * es;
+    return t;
+}
 
 // gemm_ex's choice for a checked, non-trivial FP64/FP32 product (cfg: the
 // caller's configuration or NULL); a loaded cost model is evaluated on the

@@ -67,6 +67,20 @@ static int32_t gemm_noalloc_impl(int64_t m, int64_t n, int64_t k, double alpha, 
     CallPlan cp;
     rc = plan_call(a, dtype, cfg, false, cp);
     if (rc) return rc;
+    if (cp.main_rows > 0) {
+        // the rows that fill whole rounds run whole, the tail with k cut
+        const GemmArgs t = rows_from(a, cp.main_rows, elem_size(dtype));
+        const size_t need = (size_t)cp.sp.S * t.m * t.n * elem_size(dtype);
+        if (need > SCRATCH_BYTES)
+            return set_error(MGEMM_ERR_NOMEM,
+                             "gemm_ex_noalloc: split-k needs %zu bytes of scratch, more than its "
+                             "%zu-byte maximum", need, SCRATCH_BYTES);
+        GemmArgs am = a;
+        am.m = cp.main_rows;
+        hipError_t he = (cp.al ? cp.e->launch : cp.e->launch_unaligned)(am, s);
+        if (he != hipSuccess) return hip_error(he, "gemm launch");
+        return launch_splitk_into(cp.e, t, dtype, cp.al, cp.sp, W, s);
+    }
     if (cp.sp.S > 1) {
         const size_t need = (size_t)cp.sp.S * a.m * a.n * elem_size(dtype);
         if (need > SCRATCH_BYTES)

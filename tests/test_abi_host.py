@@ -126,9 +126,9 @@ def test_choice_argument_errors(L):
              ((4, 4, 0, 4, 4, mg.F64), -3), ((4, 4, 8, 7, 4, mg.F64), -4),
              ((4, 8, 4, 4, 7, mg.F64), -5), ((4, 4, 4, 4, 4, mg.SPLIT_BF16), -6)]
     for args, code in cases:
-        assert L.mgemm_choice(*args, ctypes.byref(c), ctypes.byref(s)) == code, args
-    assert L.mgemm_choice(4, 4, 4, 4, 4, mg.F64, None, ctypes.byref(s)) == -7
-    assert L.mgemm_choice(4, 4, 4, 4, 4, mg.F64, ctypes.byref(c), None) == -8
+        assert L.mgemm_choice(*args, ctypes.byref(c), ctypes.byref(s), None) == code, args
+    assert L.mgemm_choice(4, 4, 4, 4, 4, mg.F64, None, ctypes.byref(s), None) == -7
+    assert L.mgemm_choice(4, 4, 4, 4, 4, mg.F64, ctypes.byref(c), None, None) == -8
 
 
 def test_host_alloc_argument_errors(L):

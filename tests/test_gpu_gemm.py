@@ -184,6 +184,52 @@ SPLITK_SHAPES = [(1024, 512, 4096), (1000, 999, 3001), (300, 200, 6000), (511, 1
                  (896, 1024, 1536), (300, 200, 600)]
 
 
+# outputs whose 128 x 128 tiles leave a last round of few tiles: the rows that fill
+# whole rounds run whole, the rest with k cut (FP64 3072^3: 21 + 3 tile rows, 3
+# ranges; 3584 x 3584 x 2048: 27 + 1 tile rows; 4608 x 4608 x 1536 FP32)
+SPLIT_TAIL_SHAPES = {mg.F64: [(3072, 3072, 3072), (3584, 3584, 2048)],
+                     mg.F32: [(3584, 3584, 3584), (4608, 4608, 1536)]}
+
+
+@pytest.mark.parametrize("dtype", [mg.F64, mg.F32])
+def test_split_tail(dev, orc, dtype):
+    """Split tail: 96 sampled rows (both sides of the boundary between the whole
+    rows and the tail, the first and last rows among them) within gamma_{k+2} of
+    the double-double oracle, FP64 normwise <= 1e-13; run-to-run identical; the
+    no-allocation entry point gives the same bits; the whole rows equal the 128 x
+    128 tile run whole (the same kernel), the tail rows do not (k cut)."""
+    u = 2.0 ** -24 if dtype == mg.F32 else 2.0 ** -53
+    tdt = torch.float32 if dtype == mg.F32 else torch.float64
+    for (m, n, k) in SPLIT_TAIL_SHAPES[dtype]:
+        cfg, S, main = mg.choice(m, n, k, dtype, rows=True)
+        say(f"split tail {'f32' if dtype == mg.F32 else 'f64'} shape={(m, n, k)} cfg={cfg} "
+            f"S={S} main rows={main}")
+        assert S > 1 and 0 < main < m and (cfg.bm, cfg.bn, cfg.double_buffer) == (128, 128, 2)
+        A = synth.uniform_pm1((m, k), 61 + m)
+        B = synth.uniform_pm1((k, n), 62 + n)
+        C = synth.uniform_pm1((m, n), 63 + k)
+        if dtype == mg.F32:
+            A, B, C = (x.astype(np.float32).astype(np.float64) for x in (A, B, C))
+        al, be = (np.float32(1.5), np.float32(-0.5)) if dtype == mg.F32 else (1.5, -0.5)
+        got = run_gemm(dev, A, B, C, 1.5, -0.5, dtype=dtype)
+        rows = np.unique(np.concatenate([[0, m - 1], np.arange(main - 8, main + 8),
+                                         np.linspace(1, m - 2, 78).astype(np.int64)]))
+        ref = orc.gemm_dot2(al, A[rows], B, be, C[rows], nthreads=orc.num_procs())
+        mag = 1.5 * np.abs(A[rows]) @ np.abs(B) + 0.5 * np.abs(C[rows])
+        assert np.all(np.abs(got[rows] - ref) <= gamma(k + 2, u) * mag), (m, n, k)
+        if dtype == mg.F64:
+            assert np.linalg.norm(got[rows] - ref) <= 1e-13 * np.linalg.norm(ref)
+        assert np.array_equal(got, run_gemm(dev, A, B, C, 1.5, -0.5, dtype=dtype))
+        tA, tB, tC = to_dev(A, dev, tdt), to_dev(B, dev, tdt), to_dev(C, dev, tdt)
+        mg._check(mg.gemm_ex_noalloc_raw(m, n, k, 1.5, tA.data_ptr(), k, tB.data_ptr(), n, -0.5,
+                                         tC.data_ptr(), n, dtype))
+        torch.cuda.synchronize()
+        assert np.array_equal(tC.cpu().double().numpy(), got)
+        whole = run_gemm(dev, A, B, C, 1.5, -0.5, dtype=dtype, cfg=cfg)
+        assert np.array_equal(got[:main], whole[:main])
+        assert not np.array_equal(got[main:], whole[main:])
+
+
 @pytest.mark.parametrize("dtype", [mg.F64, mg.F32])
 def test_split_k_default_choice(dev, orc, dtype):
     """Outputs whose preferred tile leaves fewer than about four work-groups per
