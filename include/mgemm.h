@@ -115,7 +115,10 @@ MGEMM_API int32_t gemm(int64_t m, int64_t n, int64_t k, double alpha,
  * the three-stage kernels can load (n, lda, ldb multiples of 16 bytes, A and B
  * 16-byte aligned), the three-stage tile (256 x 128, 128 x 128 or 64 x 64) whose
  * sustained rate times the fill of its rounds of one work-group per compute unit
- * is highest, if that fill is at least 80 %; else (m, n, k in [64, 16384]), for
+ * is highest, if that fill is at least 80 % -- or, where 128 x 128 tiles leave a
+ * last round of few tiles, the tile rows that fill whole rounds whole and the
+ * remaining rows with k cut (a split tail), where that is estimated 5 % faster;
+ * else (m, n, k in [64, 16384]), for
  * rows the three-stage kernels cannot load or where the preferred tile is a
  * two-stage one, the configuration measured fastest on the tuner's shapes of the
  * same row class in and around the (floor(log2 m), floor(log2 n), floor(log2 k))
