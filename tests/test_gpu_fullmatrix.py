@@ -9,7 +9,7 @@ default configuration choice (the kernels the sweep and the headline time).
 * FP32, N = 1024 and 4096, the same recipe on float inputs: every element within
   gamma_{k+2} with u = 2^-24 of the FP64 oracle on the same float values (plus
   the oracle's own FP64 bound).
-* Squares whose tile the round-fill rule picks (FP64 N = 3072, every element; FP64
+* Squares whose tile the round-fill rule picks (FP64 N = 2048, every element; FP64
   and FP32 N = 6144, 256 rows), within the same gamma_{k+2} bounds.
 * Emulated FP64 on the wide-range stress inputs (entries u * 2^e, e uniform in
   [-20, 20]): at N = 4096 every element, at N = 8192 256 sampled rows, against
@@ -139,12 +139,13 @@ def test_stress_inputs_against_both_oracles(dev, stress, dtype, n):
     assert e64 <= 1e-13
 
 
-@pytest.mark.parametrize("dtype,n", [(mg.F64, 3072), (mg.F64, 6144), (mg.F32, 6144)])
+@pytest.mark.parametrize("dtype,n", [(mg.F64, 2048), (mg.F64, 6144), (mg.F32, 6144)])
 def test_round_fill_squares(dev, orc, dtype, n):
-    """Squares whose tile the round-fill rule picks (N = 3072: 64 x 64, 6144: 128 x
-    128): at N = 3072 every element, at 6144 256 rows spread over the matrix,
-    within gamma_{k+2}(|A||B| + |C|) of the FP64 oracle (plus the oracle's own
-    bound), FP64 also normwise <= 1e-13."""
+    """Squares whose tile the round-fill rule picks, in whole rounds (N = 2048 and
+    6144: 128 x 128): at N = 2048 every element, at 6144 256 rows spread over the
+    matrix, within gamma_{k+2}(|A||B| + |C|) of the FP64 oracle (plus the oracle's
+    own bound), FP64 also normwise <= 1e-13.  (Squares that take a split tail are
+    checked in test_gpu_gemm.py.)"""
     cfg, splits = mg.choice(n, n, n, dtype)
     assert splits == 1 and cfg.double_buffer == 2
     say(f"round-fill square {mg.DTYPE_NAMES[dtype]} n={n}: {cfg}")
