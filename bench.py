@@ -687,7 +687,20 @@ def main():
         cpu = cpu_baseline(n, A, B, C0, args.cpu_seconds)
     del tA, tB, tC
 
-    cfg_used = (cfg if cfg is not None else mg.choice(n, n, n, mg.F64)[0]).as_dict()
+    if cfg is not None:
+        cfg_used, splits, whole_rows = cfg.as_dict(), 1, n
+    else:
+        c, splits, whole_rows = mg.choice(n, n, n, mg.F64, rows=True)
+        cfg_used = c.as_dict()
+    if splits == 1:
+        launches = kernel_name(cfg_used) + " (one launch per step)"
+    elif whole_rows == 0:
+        launches = (f"split-k of {kernel_name(cfg_used)}, k in {splits} ranges, and the sum of "
+                    "the planes (two launches per step; kernel_avg_ms is their total)")
+    else:
+        launches = (f"{kernel_name(cfg_used)} on the first {whole_rows} rows, its split-k on "
+                    f"the other {n - whole_rows} rows with k in {splits} ranges, and the sum of "
+                    "the planes (three launches per step; kernel_avg_ms is their total)")
     out = {
         "metric": METRIC,
         "value": round(tflops, 3),
@@ -706,6 +719,7 @@ def main():
                                f"{'explicit' if cfg is not None else 'library' + chr(39) + 's default'}"
                                f" tile configuration)",
                    "n": n, "alpha": 1.0, "beta": 1.0, "tile_config": cfg_used,
+                   "k_ranges": splits, "whole_rows": whole_rows,
                    "parallelism": "single GPU"},
         "pct_peak": round(100.0 * tflops / PEAK_F64_TFLOPS, 2),
         "best_step_tflops": round(flops / (best_ms * 1e-3) / 1e12, 3),
@@ -720,7 +734,7 @@ def main():
                      # profiles/gemm_pipe_f64_N8192_traffic.md (copy-calibrated)
                      "traffic": TRAFFIC_F64_N8192 if n == 8192 and cfg is None else None,
                      "traffic_unit": "bytes per launch",
-                     "kernel": kernel_name(cfg_used) + " (one launch per step)",
+                     "kernel": launches,
                      "kernel_avg_ms": round(kern_ms, 4),
                      "work_per_launch": f"2*N^3 = {flops:.4g} FLOP",
                      # Eq. 6 for the kernel's 256 x 128 tiles: the bytes with no cache
