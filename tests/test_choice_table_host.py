@@ -11,6 +11,7 @@ import pytest
 
 from paper_1706_10086_amd import tune
 from paper_1706_10086_amd.csrc import gen_choice_table as gen
+import choice_rule
 from choice_rule import library_choice, pref_choice
 
 DATA = os.path.join(os.path.dirname(tune.__file__), "data", "tune_db.json.gz")
@@ -57,3 +58,36 @@ def test_cells_name_registered_configurations(db):
             assert set(tables[w][dt].values()) <= reg
             for (lm, ln, lk) in tables[w][dt]:
                 assert all(gen.LO <= x <= gen.HI for x in (lm, ln, lk))
+
+
+def test_plan_rule_on_squares(db):
+    """The written-out plan on FP64 / FP32 squares: the whole-tile choices and the
+    N = 3072 split tail as the library's documentation states them, and for every
+    square N = 1024 ... 16384 in steps of 256 whose plan is a split tail: the whole
+    rows are whole 128-row tiles that fill whole rounds of the compute units (one
+    more tile row would not), and S x the tail's tiles fit the compute units."""
+    tables = gen.build_tables(db.records, gen.training_shapes())
+    plan = lambda dt, n: choice_rule.library_plan(tables, dt, n, n, n)
+    assert plan(0, 1024)[0][:2] == (64, 64) and plan(0, 1024)[1:] == (1, 1024)
+    assert plan(0, 2048)[0][:2] == (128, 128) and plan(0, 2048)[1] == 1
+    assert plan(0, 6144)[0][:2] == (128, 128) and plan(0, 6144)[1] == 1
+    assert plan(0, 8192)[0][:2] == (256, 128) and plan(0, 8192)[1] == 1
+    assert plan(0, 3072) == (choice_rule.PIPE128[0], 3, 21 * 128)
+    cus = choice_rule.CUS
+    tails = 0
+    for dt in (0, 1):
+        for n in range(1024, 16385, 256):
+            c, s, whole = plan(dt, n)
+            if s == 1:
+                assert whole == n
+                continue
+            tails += 1
+            assert c == choice_rule.PIPE128[dt] and 0 < whole < n and whole % 128 == 0
+            tn = -(-n // 128)
+            rows, full = whole // 128, (-(-n // 128)) * tn // cus
+            assert rows * tn <= full * cus < (rows + 1) * tn
+            assert s * (-(-n // 128) - rows) * tn <= cus
+            # k ranges: multiples of 256, the last one possibly shorter
+            kc = -(-(-(-n // s)) // 256) * 256
+            assert -(-n // kc) == s
+    assert tails >= 6

@@ -3,6 +3,7 @@ library's kernels on the shipped MI355X tuner database and evaluated on the 500
 held-out shapes (FP64 and FP32) against the exhaustive best: geometric mean of
 TFLOP/s(predicted) / TFLOP/s(best) >= 0.95, and better than the method without
 the network (one tuned configuration per dtype)."""
+import collections
 import os
 
 import numpy as np
@@ -155,11 +156,12 @@ def test_builtin_choice_runs_the_measured_configuration():
 
 
 def test_choice_c_abi_matches_the_rule():
-    """mgemm_choice (what gemm with no configuration runs, for aligned operands)
-    agrees with the rule written out in tests/choice_rule.py wherever k is not cut:
-    the round-fill rule for rows of whole 16-byte loads, the preference list and
-    the measured table otherwise; squares, held-out and aligned shapes, both
-    dtypes."""
+    """mgemm_choice (what gemm with no configuration runs, for 16-byte aligned
+    bases) agrees with the plan written out in tests/choice_rule.py -- its
+    configuration, k ranges and rows run whole -- on squares, held-out and aligned
+    shapes, long-k and out-of-range shapes and odd leading dimensions, both dtypes;
+    every branch of the plan (split-k on the two-stage and three-stage tiles, split
+    tail, round fill, preference list and measured table) is taken at least once."""
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_1706_10086_amd.csrc import gen_choice_table as gen
@@ -167,25 +169,45 @@ def test_choice_c_abi_matches_the_rule():
     mg.model_load(None)
     db = tune.load_compact(DB_PATH)
     tables = gen.build_tables(db.records, gen.training_shapes())
-    shapes = [(n, n, n) for n in (512, 1024, 1536, 2048, 2560, 3072, 4096, 5120, 6144, 8192)]
-    shapes += tune.shape_set("heldout")[:150] + tune.shape_set("aligned")[:100]
-    checked = 0
+    squares = (512, 1024, 1536, 2048, 2560, 3072, 3584, 4096, 4608, 5120, 6144, 7168, 8192,
+               9216, 12288, 16384, 20480)
+    shapes = [(n, n, n, n, n) for n in squares]
+    shapes += [(m, n, k, k, n) for (m, n, k) in
+               tune.shape_set("heldout")[:150] + tune.shape_set("aligned")[:100]]
+    # long k and shapes outside the measured range (split-k first)
+    shapes += [(m, n, k, k, n) for (m, n, k) in
+               ((256, 256, 8192), (512, 512, 16384), (128, 256, 20000), (64, 64, 4096),
+                (1000, 1000, 3000), (100, 100, 30000), (40, 3000, 5000), (3000, 48, 2500))]
+    # leading dimensions that break or keep the 16-byte rows
+    shapes += [(6144, 6144, 6144, 6145, 6144), (3072, 3072, 3072, 3072, 3073),
+               (3072, 3072, 3072, 3076, 3072), (512, 512, 16384, 16385, 512)]
+    branches = collections.Counter()
     for dt in (mg.F64, mg.F32):
-        for (m, n, k) in shapes:
-            cfg, splits = mg.choice(m, n, k, dt)
+        for (m, n, k, lda, ldb) in shapes:
+            cfg, splits, whole = mg.choice(m, n, k, dt, lda=lda, ldb=ldb, rows=True)
+            want = host.library_plan(tables, dt, m, n, k, lda, ldb)
+            assert (cfg.as_tuple(), splits, whole) == want, (dt, m, n, k, lda, ldb)
+            c = want[0]
             if splits > 1:
-                continue
-            assert cfg.as_tuple() == host.library_choice(tables, dt, m, n, k), (dt, m, n, k)
-            checked += 1
-    print(f"  {checked} choices agree", flush=True)
-    assert checked >= 400
-    # the round-fill rule on FP64 squares
+                branches["split tail" if whole else
+                          "split-k, three-stage" if c[5] == 2 else "split-k, two-stage"] += 1
+            elif c == host.pref_choice(dt, m, n):
+                branches["preference list"] += 1
+            elif c[5] == 2:
+                branches["round fill"] += 1
+            else:
+                branches["measured table"] += 1
+    print(f"  {sum(branches.values())} plans agree: {dict(branches)}", flush=True)
+    assert sum(branches.values()) >= 500
+    assert len(branches) == 6 and min(branches.values()) >= 2, branches
+    # the plans stated for squares: FP64 N = 1024 64 x 64, 6144 128 x 128, 8192
+    # 256 x 128, all whole; 3072 21 tile rows whole and the last 3 in 3 k ranges
     assert mg.choice(1024, 1024, 1024)[0].as_tuple()[:2] == (64, 64)
     assert mg.choice(6144, 6144, 6144)[0].as_tuple()[:2] == (128, 128)
     assert mg.choice(8192, 8192, 8192)[0].as_tuple()[:2] == (256, 128)
+    c3, s3, r3 = mg.choice(3072, 3072, 3072, rows=True)
+    assert (c3.as_tuple()[:2], s3, r3) == ((128, 128), 3, 2688)
     # an odd leading dimension of A breaks the 16-byte rows: the measured table's
-    # cell for that row class decides (the rule's row class follows lda, here k + 1)
+    # cell for that row class decides
     c_odd, s_odd = mg.choice(6144, 6144, 6144, lda=6145)
-    assert s_odd == 1
-    assert c_odd.as_tuple() == host.library_choice(tables, mg.F64, 6144, 6144, 6145)
-    assert c_odd.double_buffer != 2
+    assert s_odd == 1 and c_odd.double_buffer != 2
