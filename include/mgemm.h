@@ -117,7 +117,8 @@ MGEMM_API int32_t gemm(int64_t m, int64_t n, int64_t k, double alpha,
  * sustained rate times the fill of its rounds of one work-group per compute unit
  * is highest, if that fill is at least 80 % -- or, where 128 x 128 tiles leave a
  * last round of few tiles, the tile rows that fill whole rounds whole and the
- * remaining rows with k cut (a split tail), where that is estimated 5 % faster;
+ * remaining rows with k cut (a split tail), where that is estimated 5 % faster
+ * than the best single tile (2 % where that tile is 128 x 128 or 256 x 128);
  * else (m, n, k in [64, 16384]), for
  * rows the three-stage kernels cannot load or where the preferred tile is a
  * two-stage one, the configuration measured fastest on the tuner's shapes of the

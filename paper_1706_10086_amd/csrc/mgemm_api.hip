@@ -359,8 +359,10 @@ static const PipeRate kPipeRatesF32[] = {{{256, 128, 32, 8, 4, 2, 2}, 141.0},
 constexpr double WAVE_FILL_MIN = 0.8;
 
 // best_tf: the highest rate x fill among the tiles (0 without a device).
-static const KernelEntry *wave_filled_pipe(const GemmArgs &a, int32_t dtype, double *best_tf) {
+static const KernelEntry *wave_filled_pipe(const GemmArgs &a, int32_t dtype, double *best_tf,
+                                           bool *best_large) {
     *best_tf = 0.0;
+    *best_large = false;
     const int cus = compute_units();
     if (cus <= 0) return nullptr;
     const PipeRate *pr = dtype == MGEMM_F32 ? kPipeRatesF32 : kPipeRatesF64;
@@ -379,6 +381,7 @@ static const KernelEntry *wave_filled_pipe(const GemmArgs &a, int32_t dtype, dou
         }
     }
     *best_tf = score;
+    *best_large = best >= 0 && pr[best].cfg.bm * pr[best].cfg.bn >= 128 * 128;
     if (best < 0 || fill_best < WAVE_FILL_MIN) return nullptr;
     int cnt = 0;
     const KernelEntry *reg = registry(dtype, &cnt);
@@ -391,14 +394,19 @@ static const KernelEntry *wave_filled_pipe(const GemmArgs &a, int32_t dtype, dou
 // about 1/S of a round plus the sum of the S partial planes.  Taken when the
 // estimate -- the main part at the tile's rate x its fill, the tail at
 // TAIL_RATE_FACTOR of that rate x its fill (shorter k-loops), the sum at
-// SUM_BYTES_PER_S -- beats plain_tf, the best single-tile estimate, by TAIL_GAIN.
+// SUM_BYTES_PER_S -- beats plain_tf, the best single-tile estimate, by TAIL_GAIN,
+// or by TAIL_GAIN_LARGE where that tile is a 128 x 128 or 256 x 128 one.
 // (N = 3072 FP64: 21 of 24 tile rows whole in two full rounds, 3 rows in 3 ranges
-// of 1024: 53 -> 65 TFLOP/s.)
+// of 1024: 53 -> 65 TFLOP/s.  On the tuner's shapes whose estimate beat the best
+// single tile by 2-5 %, the tail measured 1.003-1.073x as fast where that tile was
+// 128 x 128 or 256 x 128, but 0.93-1.07x where it was 64 x 64.)
 constexpr double TAIL_RATE_FACTOR = 0.8;
 constexpr double SUM_BYTES_PER_S = 4e12;
 constexpr double TAIL_GAIN = 1.05;
+constexpr double TAIL_GAIN_LARGE = 1.02;
 
-static bool split_tail_plan(const GemmArgs &a, int32_t dtype, double plain_tf, CallPlan &cp) {
+static bool split_tail_plan(const GemmArgs &a, int32_t dtype, double plain_tf, bool plain_large,
+                            CallPlan &cp) {
     const int cus = compute_units();
     if (cus <= 0 || !pipe_splitk_eligible(a, dtype)) return false;
     const PipeRate &p = (dtype == MGEMM_F32 ? kPipeRatesF32 : kPipeRatesF64)[1];   // 128 x 128
@@ -420,7 +428,7 @@ static bool split_tail_plan(const GemmArgs &a, int32_t dtype, double plain_tf, C
                          (double)elem_size(dtype) / SUM_BYTES_PER_S;
     const double t = wm / (p.tflops * fill_m) + (w - wm) / (p.tflops * TAIL_RATE_FACTOR * fill_t) +
                      sum_s;
-    if (w / t < TAIL_GAIN * plain_tf) return false;
+    if (w / t < (plain_large ? TAIL_GAIN_LARGE : TAIL_GAIN) * plain_tf) return false;
     int cnt = 0;
     const KernelEntry *reg = registry(dtype, &cnt);
     const KernelEntry *e = find_entry(reg, cnt, p.cfg);
@@ -470,8 +478,9 @@ int32_t plan_call(const GemmArgs &a, int32_t dtype, const mgemm_cfg *cfg,
         // fills them well enough
         if (rows16) {
             double best_tf = 0.0;
-            const KernelEntry *q = wave_filled_pipe(a, dtype, &best_tf);
-            if (split_tail_plan(a, dtype, best_tf, cp)) return 0;
+            bool best_large = false;
+            const KernelEntry *q = wave_filled_pipe(a, dtype, &best_tf, &best_large);
+            if (split_tail_plan(a, dtype, best_tf, best_large, cp)) return 0;
             if (q) {
                 cp.e = q;
                 return 0;

@@ -10,8 +10,8 @@ where the list names a two-stage configuration.
 library_plan (what mgemm_choice reports): first split-k, for k >= 2048 or a shape
 outside the measured range, where the preferred tile is a small one that leaves the
 compute units short of work; then, for rows of whole 16-byte loads, a split tail
-where its time estimate beats the best single three-stage tile by 5 %; then
-library_choice."""
+where its time estimate beats the best single three-stage tile by 5 % (2 % where
+that tile is 128 x 128 or 256 x 128); then library_choice."""
 from paper_1706_10086_amd.csrc import gen_choice_table as gen
 
 # the preference list: (configuration, minimum C tiles to take it)
@@ -82,7 +82,8 @@ TWO_STAGE_SPLITK = {0: {(64, 64, 16, 4, 2, 1, 0), (32, 32, 16, 1, 2, 1, 0)}, 1: 
 PIPE128 = {0: PIPE_RATES[0][1][0], 1: PIPE_RATES[1][1][0]}
 # the split tail's estimate: the tail at this fraction of the tile's rate, the sum
 # of the partial planes at this many bytes per second, and the gain it must reach
-TAIL_RATE_FACTOR, SUM_BYTES_PER_S, TAIL_GAIN = 0.8, 4e12, 1.05
+# over the best single tile (over a 128 x 128 or 256 x 128 one: TAIL_GAIN_LARGE)
+TAIL_RATE_FACTOR, SUM_BYTES_PER_S, TAIL_GAIN, TAIL_GAIN_LARGE = 0.8, 4e12, 1.05, 1.02
 
 
 def _cdiv(a, b):
@@ -137,11 +138,12 @@ def splitk_plan(dt, m, n, k, lda, ldb, pref):
     return (s, pref) if s > 1 else (1, None)
 
 
-def split_tail(dt, m, n, k, lda, ldb, plain_tf):
+def split_tail(dt, m, n, k, lda, ldb, plain_tf, plain_large=False):
     """(k ranges, rows run whole) of a split tail with the 128 x 128 tile, or None:
     the tile rows that fill whole rounds run whole, the other rows with k cut so
     that S x their tiles fit the compute units; taken when the estimate beats
-    plain_tf (the best single tile's rate x fill) by TAIL_GAIN."""
+    plain_tf (the best single tile's rate x fill) by TAIL_GAIN, or by
+    TAIL_GAIN_LARGE where that tile is 128 x 128 or larger (plain_large)."""
     if not pipe_split_eligible(dt, n, k, lda, ldb):
         return None
     rate = PIPE_RATES[dt][1][1]
@@ -164,7 +166,7 @@ def split_tail(dt, m, n, k, lda, ldb, plain_tf):
     es = 4 if dt == 1 else 8
     t = (wm / (rate * fill_m) + (w - wm) / (rate * TAIL_RATE_FACTOR * fill_t)
          + (s + 2) * (m - main_rows) * n * es / SUM_BYTES_PER_S)
-    if w / t < TAIL_GAIN * plain_tf:
+    if w / t < (TAIL_GAIN_LARGE if plain_large else TAIL_GAIN) * plain_tf:
         return None
     return s, main_rows
 
@@ -185,7 +187,7 @@ def library_plan(tables, dt, m, n, k, lda=None, ldb=None):
     whole = rows16(dt, n, lda, ldb)
     if whole:
         q, score, fill = _best_filled_pipe(dt, m, n)
-        tail = split_tail(dt, m, n, k, lda, ldb, score)
+        tail = split_tail(dt, m, n, k, lda, ldb, score, q[0] * q[1] >= 128 * 128)
         if tail is not None:
             return PIPE128[dt], tail[0], tail[1]
         if fill >= WAVE_FILL_MIN:

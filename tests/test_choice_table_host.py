@@ -73,6 +73,10 @@ def test_plan_rule_on_squares(db):
     assert plan(0, 6144)[0][:2] == (128, 128) and plan(0, 6144)[1] == 1
     assert plan(0, 8192)[0][:2] == (256, 128) and plan(0, 8192)[1] == 1
     assert plan(0, 3072) == (choice_rule.PIPE128[0], 3, 21 * 128)
+    # N = 7680: 128 x 128 tiles whole in 14.06 rounds; the tail (one tile row of 60
+    # tiles in 4 k ranges) is estimated 4.7 % faster, over the 2 % a 128 x 128 best
+    # tile asks for
+    assert plan(0, 7680) == (choice_rule.PIPE128[0], 4, 59 * 128)
     cus = choice_rule.CUS
     tails = 0
     for dt in (0, 1):
