@@ -262,9 +262,11 @@ def leg_parity(mg, torch, dev):
             "rel_err": float(np.linalg.norm(got - want) / np.linalg.norm(want))}
 
 
-def leg_sweep(mg, torch, dev, sizes=(1024, 2048, 4096, 6144, 8192, 16384)):
+def leg_sweep(mg, torch, dev, sizes=(1024, 2048, 3072, 4096, 6144, 7680, 8192, 16384)):
     """The square sweep: FP64 and FP32 with the library's default configuration,
-    uniform[-1,1) inputs drawn on the device, alpha = beta = 1."""
+    uniform[-1,1) inputs drawn on the device, alpha = beta = 1; each size records
+    the plan (tile, k ranges, rows run whole), and where the plan is a split tail
+    (N = 3072 FP64, 7680) also the rate of its 128 x 128 tile run whole."""
     log("bench: square sweep, FP64 and FP32")
     stream = torch.cuda.current_stream()
     out = {"inputs": "uniform[-1,1) on the device, alpha = beta = 1",
@@ -283,9 +285,17 @@ def leg_sweep(mg, torch, dev, sizes=(1024, 2048, 4096, 6144, 8192, 16384)):
                                batches=5 if n <= 8192 else 3)
             ms = float(np.mean(ts))
             tf = 2.0 * n ** 3 / ms / 1e9
-            out[name][str(n)] = {"ms": round(ms, 4), "tflops": round(tf, 3),
-                                 "pct_peak": round(100 * tf / peak, 2),
-                                 "best_tflops": round(2.0 * n ** 3 / min(ts) / 1e9, 3)}
+            c, splits, whole = mg.choice(n, n, n, dt, rows=True)
+            rec = {"ms": round(ms, 4), "tflops": round(tf, 3),
+                   "pct_peak": round(100 * tf / peak, 2),
+                   "best_tflops": round(2.0 * n ** 3 / min(ts) / 1e9, 3),
+                   "plan": {"tile": f"{c.bm}x{c.bn}x{c.bk}", "k_ranges": splits,
+                            "whole_rows": whole}}
+            if splits > 1 and whole > 0:
+                tw = timed_batches(lambda: mg.gemm(A, B, C, 1.0, 1.0, cfg=c, stream=stream),
+                                   stream, batches=3)
+                rec["tile_whole_tflops"] = round(2.0 * n ** 3 / float(np.mean(tw)) / 1e9, 3)
+            out[name][str(n)] = rec
             log(f"  {name} N={n}: {ms:.3f} ms, {tf:.1f} TFLOP/s")
             del A, B, C
         torch.cuda.empty_cache()
