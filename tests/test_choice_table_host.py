@@ -95,3 +95,48 @@ def test_plan_rule_on_squares(db):
             kc = -(-(-(-n // s)) // 256) * 256
             assert -(-n // kc) == s
     assert tails >= 6
+
+
+def test_written_out_rule_uses_the_library_constants():
+    """tests/choice_rule.py restates the plan with the library's own constants:
+    preference lists, three-stage rates, fill and tail thresholds, split-k limits,
+    the measured range and the tiles registered with a two-stage split-k kernel,
+    read here from the C sources (the GPU test then checks the plans themselves)."""
+    import re
+    csrc = os.path.join(os.path.dirname(gen.__file__))
+    api = open(os.path.join(csrc, "mgemm_api.hip")).read()
+    tiled = open(os.path.join(csrc, "gemm_tiled.hip")).read()
+    table = open(os.path.join(csrc, "choice_table.h")).read()
+
+    def const(name, text=api):
+        return float(re.search(rf"constexpr \w+ {name} = ([0-9.e]+);", text).group(1))
+
+    def block(name):
+        return api[api.index(name):api.index("};", api.index(name))]
+
+    cfg = r"\{\{?(\d+), (\d+), (\d+), (\d+), (\d+), (\d+), (\d+)\}, ([0-9.]+)\}"
+    for dt, suffix in ((0, "F64"), (1, "F32")):
+        pref = [(tuple(int(x) for x in g[:7]), int(g[7]))
+                for g in re.findall(cfg, block(f"kPref{suffix}[]"))]
+        assert pref == choice_rule.PREF[dt]
+        rates = [(tuple(int(x) for x in g[:7]), float(g[7]))
+                 for g in re.findall(cfg, block(f"kPipeRates{suffix}[]"))]
+        assert rates == choice_rule.PIPE_RATES[dt]
+    assert const("WAVE_FILL_MIN") == choice_rule.WAVE_FILL_MIN
+    assert const("TAIL_RATE_FACTOR") == choice_rule.TAIL_RATE_FACTOR
+    assert const("SUM_BYTES_PER_S") == choice_rule.SUM_BYTES_PER_S
+    assert const("TAIL_GAIN") == choice_rule.TAIL_GAIN
+    assert const("TAIL_GAIN_LARGE") == choice_rule.TAIL_GAIN_LARGE
+    assert const("SPLITK_MIN_K") == choice_rule.SPLITK_MIN_K
+    assert const("SPLITK_FIRST_K") == choice_rule.SPLITK_FIRST_K
+    assert const("SPLITK_MAX") == choice_rule.SPLITK_MAX
+    assert 2 ** const("CHOICE_LOG2_LO", table) == choice_rule.MEASURED_LO
+    assert 2 ** const("CHOICE_LOG2_HI", table) == choice_rule.MEASURED_HI
+    # two-stage split-k kernels: MGEMM_REG_SPLITK(T, BM, BN, BK, WGM, WGN, EPT, DBUF, OCC)
+    regs = {0: set(), 1: set()}
+    for t, *v in re.findall(r"^\s*MGEMM_REG_SPLITK\((\w+), (\d+), (\d+), (\d+), (\d+), (\d+), "
+                            r"(\d+), (\d+), (\d+)\)", tiled, flags=re.M):
+        bm, bn, bk, wgm, wgn, ept, dbuf, occ = (int(x) for x in v)
+        regs[1 if t == "float" else 0].add((bm, bn, bk, wgm * wgn, ept, dbuf, occ))
+    assert regs == choice_rule.TWO_STAGE_SPLITK
+    assert choice_rule.CUS == 256
